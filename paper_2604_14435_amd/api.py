@@ -1,0 +1,227 @@
+"""Torch-facing wrappers of the C ABI: argument marshalling only.
+
+Every function takes CUDA (HIP) tensors, passes their device pointers and
+the current stream to libdvq.so, and returns tensors allocated by torch.  No
+arithmetic of the method happens here.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+ENTANGLERS = {"cz": L.DVQ_ENT_CZ_LADDER, "cnot": L.DVQ_ENT_CNOT_LADDER}
+KINDS = {"global": L.DVQ_COST_GLOBAL, "local": L.DVQ_COST_LOCAL}
+PRECISIONS = {"f64": L.DVQ_F64, "f32": L.DVQ_F32}
+EXECS = {"literal": L.DVQ_EXEC_LITERAL, "generic": L.DVQ_EXEC_GENERIC}
+
+
+@dataclass(frozen=True)
+class AnsatzSpec:
+    """V(theta): `layers` layers of RY on each of `n` qubits + a ladder."""
+    n: int
+    layers: int
+    entangler: str = "cz"
+
+    @property
+    def P(self) -> int:
+        return self.n * self.layers
+
+    def c(self) -> L.Ansatz:
+        return L.Ansatz(self.n, self.layers, ENTANGLERS[self.entangler])
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(t: torch.Tensor | None = None):
+    dev = t.device if t is not None else None
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _cuda(t: torch.Tensor, dtype, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    return t.contiguous()
+
+
+def _b_args(b_kind: str, b):
+    if b_kind == "plus":
+        return L.DVQ_B_PLUS, None
+    return L.DVQ_B_VECTOR, _cuda(b, torch.float64, "b")
+
+
+# -------------------------------------------------------------- decomposition
+
+def pauli_decompose_dense(A: torch.Tensor) -> torch.Tensor:
+    """All 4^n coefficients, complex128 [N, N] indexed [x, z]."""
+    A = _cuda(A, torch.float64, "A")
+    N = A.shape[0]
+    n = N.bit_length() - 1
+    lib = L.load()
+    ws = torch.empty(max(1, lib.dvq_decompose_workspace_bytes(n)), dtype=torch.uint8, device=A.device)
+    out = torch.empty((N, N), dtype=torch.complex128, device=A.device)
+    L.call("dvq_pauli_decompose_dense", _p(A), n, _p(out), _p(ws), ws.numel(), _stream(A))
+    return out
+
+
+def pauli_decompose(A: torch.Tensor, tau: float | None = None, top_L: int | None = None,
+                    capacity: int = 65536):
+    """Kept terms in ranking order: (coeffs complex128 [L], strings int32 [L, 2] = (x, z),
+    relative Frobenius error)."""
+    A = _cuda(A, torch.float64, "A")
+    N = A.shape[0]
+    n = N.bit_length() - 1
+    lib = L.load()
+    ws = torch.empty(lib.dvq_decompose_workspace_bytes(n), dtype=torch.uint8, device=A.device)
+    coeffs = torch.empty(capacity, dtype=torch.complex128, device=A.device)
+    strings = torch.empty((capacity, 2), dtype=torch.int32, device=A.device)
+    lout = ctypes.c_int64(0)
+    ferr = ctypes.c_double(0.0)
+    L.call("dvq_pauli_decompose", _p(A), n, float(tau if tau is not None else 0.0),
+           int(top_L if top_L is not None else 0), _p(coeffs), _p(strings), capacity,
+           ctypes.byref(lout), ctypes.byref(ferr), _p(ws), ws.numel(), _stream(A))
+    k = lout.value
+    return coeffs[:k].clone(), strings[:k].clone(), ferr.value
+
+
+# -------------------------------------------------------------- circuits / cost
+
+def circuit_count(n: int, L_: int, kind: str) -> int:
+    return int(L.load().dvq_circuit_count(n, L_, KINDS[kind]))
+
+
+def vqls_terms(ansatz: AnsatzSpec, theta: torch.Tensor, strings: torch.Tensor, kind: str = "local",
+               precision: str = "f64", b_kind: str = "plus", b: torch.Tensor | None = None,
+               exec_: str = "literal", out=None):
+    """(beta [B, L, L], other) complex128; other = delta [B, n, L, L] or gamma [B, L]."""
+    theta = _cuda(theta, torch.float64, "theta")
+    if theta.dim() == 1:
+        theta = theta.unsqueeze(0)
+    strings = _cuda(strings, torch.int32, "strings")
+    B, Lt, n = theta.shape[0], strings.shape[0], ansatz.n
+    if out is None:
+        beta = torch.empty((B, Lt, Lt), dtype=torch.complex128, device=theta.device)
+        oshape = (B, n, Lt, Lt) if kind == "local" else (B, Lt)
+        other = torch.empty(oshape, dtype=torch.complex128, device=theta.device)
+    else:
+        beta, other = out
+    bk, bt = _b_args(b_kind, b)
+    a = ansatz.c()
+    L.call("dvq_vqls_terms", ctypes.byref(a), _p(theta), B, PRECISIONS[precision], _p(strings), Lt,
+           bk, _p(bt), KINDS[kind], EXECS[exec_], _p(beta), _p(other), _stream(theta))
+    return beta, other
+
+
+def vqls_cost(coeffs: torch.Tensor, n: int, kind: str, beta: torch.Tensor, other: torch.Tensor,
+              out=None):
+    """(C [B] float64, parts [B, 2] complex128 = (E or G, Psi))."""
+    coeffs = _cuda(coeffs, torch.complex128, "coeffs")
+    beta = _cuda(beta, torch.complex128, "beta")
+    other = _cuda(other, torch.complex128, "other")
+    B = beta.shape[0]
+    if out is None:
+        C = torch.empty(B, dtype=torch.float64, device=beta.device)
+        parts = torch.empty((B, 2), dtype=torch.complex128, device=beta.device)
+    else:
+        C, parts = out
+    L.call("dvq_vqls_cost", _p(coeffs), coeffs.shape[0], n, KINDS[kind], _p(beta), _p(other), B,
+           _p(C), _p(parts), _stream(beta))
+    return C, parts
+
+
+class ShiftWorkspace:
+    """Scratch memory of the parameter-shift gradient, allocated once."""
+
+    def __init__(self, ansatz: AnsatzSpec, L_: int, kind: str, device):
+        a = ansatz.c()
+        nbytes = L.load().dvq_grad_shift_workspace_bytes(ctypes.byref(a), L_, KINDS[kind])
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def vqls_grad_shift(ansatz: AnsatzSpec, theta: torch.Tensor, coeffs: torch.Tensor,
+                    strings: torch.Tensor, kind: str = "local", precision: str = "f64",
+                    b_kind: str = "plus", b=None, workspace: ShiftWorkspace | None = None, out=None):
+    """Plain path: (C [1], grad [P]) by the parameter-shift rule."""
+    theta = _cuda(theta, torch.float64, "theta").reshape(-1)
+    coeffs = _cuda(coeffs, torch.complex128, "coeffs")
+    strings = _cuda(strings, torch.int32, "strings")
+    if workspace is None:
+        workspace = ShiftWorkspace(ansatz, strings.shape[0], kind, theta.device)
+    if out is None:
+        C = torch.empty(1, dtype=torch.float64, device=theta.device)
+        grad = torch.empty(ansatz.P, dtype=torch.float64, device=theta.device)
+    else:
+        C, grad = out
+    bk, bt = _b_args(b_kind, b)
+    a = ansatz.c()
+    L.call("dvq_vqls_grad_shift", ctypes.byref(a), _p(theta), PRECISIONS[precision], _p(coeffs),
+           _p(strings), strings.shape[0], bk, _p(bt), KINDS[kind], _p(C), _p(grad),
+           _p(workspace.buf), workspace.buf.numel(), _stream(theta))
+    return C, grad
+
+
+def vqls_grad_adjoint(ansatz: AnsatzSpec, theta: torch.Tensor, coeffs: torch.Tensor,
+                      strings: torch.Tensor, kind: str = "local", precision: str = "f32",
+                      b_kind: str = "plus", b=None, per_row_system: bool = False, out=None):
+    """Fast path: (C [B], grad [B, P]) by the adjoint sweep."""
+    theta = _cuda(theta, torch.float64, "theta")
+    if theta.dim() == 1:
+        theta = theta.unsqueeze(0)
+    coeffs = _cuda(coeffs, torch.complex128, "coeffs")
+    strings = _cuda(strings, torch.int32, "strings")
+    B = theta.shape[0]
+    Lt = strings.shape[-2]
+    if out is None:
+        C = torch.empty(B, dtype=torch.float64, device=theta.device)
+        grad = torch.empty((B, ansatz.P), dtype=torch.float64, device=theta.device)
+    else:
+        C, grad = out
+    bk, bt = _b_args(b_kind, b)
+    a = ansatz.c()
+    L.call("dvq_vqls_grad_adjoint", ctypes.byref(a), _p(theta), B, PRECISIONS[precision],
+           _p(coeffs), _p(strings), Lt, int(per_row_system), bk, _p(bt), KINDS[kind], _p(C),
+           _p(grad), _stream(theta))
+    return C, grad
+
+
+class AdjointCost(torch.autograd.Function):
+    """C(theta) with the adjoint kernel's gradient as its backward."""
+
+    @staticmethod
+    def forward(ctx, theta, ansatz, coeffs, strings, kind, precision, b_kind, b):
+        C, grad = vqls_grad_adjoint(ansatz, theta.detach(), coeffs, strings, kind, precision, b_kind, b)
+        ctx.save_for_backward(grad)
+        ctx.shape = theta.shape
+        return C if theta.dim() > 1 else C[0]
+
+    @staticmethod
+    def backward(ctx, gC):
+        (grad,) = ctx.saved_tensors
+        g = grad * (gC.reshape(-1, 1) if gC.dim() > 0 else gC)
+        return g.reshape(ctx.shape), None, None, None, None, None, None, None
+
+
+def gd_step(theta: torch.Tensor, grad: torch.Tensor, lr: float) -> None:
+    """theta -= lr * grad, in place."""
+    if not theta.is_contiguous() or not grad.is_contiguous():
+        raise ValueError("gd_step needs contiguous tensors")
+    L.call("dvq_gd_step", _p(theta), _p(grad), theta.numel(), float(lr), _stream(theta))
+
+
+def fidelity(ansatz: AnsatzSpec, theta: torch.Tensor, target: torch.Tensor) -> torch.Tensor:
+    """|<target|V(theta)|0>|^2 per row, float64 [B]."""
+    theta = _cuda(theta, torch.float64, "theta")
+    if theta.dim() == 1:
+        theta = theta.unsqueeze(0)
+    target = _cuda(target, torch.complex128, "target")
+    F = torch.empty(theta.shape[0], dtype=torch.float64, device=theta.device)
+    a = ansatz.c()
+    L.call("dvq_fidelity", ctypes.byref(a), _p(theta), theta.shape[0], _p(target), _p(F), _stream(theta))
+    return F

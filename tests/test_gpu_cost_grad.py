@@ -1,0 +1,188 @@
+"""GPU parity: cost assembly, parameter-shift and adjoint gradients, gradient
+descent and fidelity vs the oracle.
+
+Bars: cost within 1e-6 absolute (1e-12 in float64 where both sides are
+float64 end to end); gradients: adjoint float64 == exact shift rule within
+1e-10, float32 within 1e-5; trajectory theta within 1e-10 after 50 steps.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import circuit as qc
+from oracle import cost as oc
+from oracle import linalg as ola
+from oracle import pauli as op
+from workloads import plus_state, random_unit_vector, theta_uniform, toeplitz
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_2604_14435_amd import api  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _system(n, a, b, tau=None, top_L=None):
+    A = toeplitz(n, a, b)
+    C = op.decompose_fwht(A)
+    keep = op.select_tau(C, tau) if tau is not None else op.select_top(C, top_L)
+    c, xs, zs = op.kept_terms(C, keep)
+    strings = np.stack([xs, zs], axis=1).astype(np.int32)
+    At = op.reconstruct(c, xs, zs, n)
+    return A, At, c, xs, zs, strings
+
+
+@pytest.mark.parametrize("kind", ["global", "local"])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_cost_from_terms_small(kind, precision):
+    n, layers = 3, 2
+    A, At, c, xs, zs, strings = _system(n, 1.0, -0.4, tau=0.01)
+    th = theta_uniform(n * layers, seed=0)
+    an = api.AnsatzSpec(n, layers, "cz")
+    beta, other = api.vqls_terms(an, _gpu(th), _gpu(strings), kind, precision)
+    C, parts = api.vqls_cost(_gpu(c), n, kind, beta, other)
+    wb, wo = qc.terms(th, n, layers, "cz", xs, zs, kind)
+    want = oc.cost_from_terms(c, wb, wo, n, kind)
+    tol = 1e-12 if precision == "f64" else 1e-6
+    assert abs(C.item() - want) < tol
+    num, psi = oc.aggregate(c, wb, wo, kind)
+    p = parts[0].cpu().numpy()
+    assert abs(p[0] - num) < (1e-11 if precision == "f64" else 1e-5)
+    assert abs(p[1] - psi) < (1e-11 if precision == "f64" else 1e-5)
+
+
+def test_cost_n10_L64_both_precisions():
+    """Cost of the full n = 10, L = 64 evaluation vs the dense definition."""
+    n, layers = 10, 4
+    A, At, c, xs, zs, strings = _system(n, 1.0, -0.45, tau=0.01)
+    th = theta_uniform(n * layers, seed=0)
+    x = qc.ansatz_state(th, n, layers)
+    want = oc.cost_dense(At, x, n, "local")
+    an = api.AnsatzSpec(n, layers, "cz")
+    for precision, tol in (("f64", 1e-12), ("f32", 1e-6)):
+        beta, delta = api.vqls_terms(an, _gpu(th), _gpu(strings), "local", precision)
+        C, _ = api.vqls_cost(_gpu(c), n, "local", beta, delta)
+        assert abs(C.item() - want) < tol, precision
+
+
+@pytest.mark.parametrize("kind", ["global", "local"])
+def test_shift_rule_gradient_small(kind):
+    n, layers = 3, 2
+    A, At, c, xs, zs, strings = _system(n, 1.0, -0.4, tau=0.01)
+    th = theta_uniform(n * layers, seed=0)
+    an = api.AnsatzSpec(n, layers, "cz")
+    C, g = api.vqls_grad_shift(an, _gpu(th), _gpu(c), _gpu(strings), kind, "f64")
+    parts = lambda t: oc.parts_theta_dense(t, At, n, layers, "cz", kind)
+    C0, g0 = oc.grad_parameter_shift(parts, th, n, kind)
+    assert abs(C.item() - C0) < 1e-12
+    assert np.max(np.abs(g.cpu().numpy() - g0)) < 1e-10
+
+
+@pytest.mark.parametrize("kind", ["global", "local"])
+@pytest.mark.parametrize("ent", ["cz", "cnot"])
+@pytest.mark.parametrize("b_kind", ["plus", "vector"])
+def test_adjoint_matches_shift_rule_and_fd(kind, ent, b_kind):
+    n, layers = 4, 3
+    A, At, c, xs, zs, strings = _system(n, 1.0, -0.4, top_L=12)
+    b = random_unit_vector(1 << n, seed=8) if b_kind == "vector" else None
+    th = theta_uniform(n * layers, seed=1)
+    an = api.AnsatzSpec(n, layers, ent)
+    parts = lambda t: oc.parts_theta_dense(t, At, n, layers, ent, kind, b_kind, b)
+    C0, g0 = oc.grad_parameter_shift(parts, th, n, kind)
+    gfd = oc.grad_finite_difference(lambda t: oc.cost_theta_dense(t, At, n, layers, ent, kind, b_kind, b), th)
+    assert np.max(np.abs(g0 - gfd)) < 1e-7
+    for precision, tol in (("f64", 1e-10), ("f32", 1e-5)):
+        C, g = api.vqls_grad_adjoint(an, _gpu(th), _gpu(c), _gpu(strings), kind, precision, b_kind,
+                                     None if b is None else _gpu(b))
+        assert abs(C.item() - C0) < (1e-12 if precision == "f64" else 1e-6)
+        assert np.max(np.abs(g[0].cpu().numpy() - g0)) < tol, precision
+
+
+def test_adjoint_n10_L128_six_layers():
+    """n = 10, tau = 0.005 -> L = 128, 6 layers (60 parameters): adjoint vs the
+    exact shift rule (dense route) and central differences (h = 1e-4)."""
+    n, layers = 10, 6
+    A, At, c, xs, zs, strings = _system(n, 1.0, -0.45, tau=0.005)
+    assert len(xs) == 128
+    th = theta_uniform(n * layers, seed=0)
+    an = api.AnsatzSpec(n, layers, "cz")
+    parts = lambda t: oc.parts_theta_dense(t, At, n, layers, "cz", "local")
+    C0, g0 = oc.grad_parameter_shift(parts, th, n, "local")
+    f = lambda t: oc.cost_theta_dense(t, At, n, layers, "cz", "local")
+    gfd = oc.grad_finite_difference(f, th, 1e-4)
+    assert np.max(np.abs(g0 - gfd)) < 1e-7
+    for precision, tol in (("f64", 1e-10), ("f32", 1e-5)):
+        C, g = api.vqls_grad_adjoint(an, _gpu(th), _gpu(c), _gpu(strings), "local", precision)
+        assert abs(C.item() - C0) < (1e-12 if precision == "f64" else 1e-6)
+        assert np.max(np.abs(g[0].cpu().numpy() - g0)) < tol
+
+
+def test_adjoint_per_row_systems():
+    """B = 4 rows, each with its own Toeplitz system (the warm-start data path)."""
+    n, layers = 5, 2
+    rows = []
+    for i, (a, b) in enumerate([(1.0, -0.3), (0.9, -0.45), (1.2, -0.1), (0.8, -0.2)]):
+        rows.append(_system(n, a, b, top_L=16))
+    coeffs = np.stack([r[2] for r in rows])
+    strings = np.stack([r[5] for r in rows])
+    th = theta_uniform(4 * n * layers, seed=3).reshape(4, -1)
+    an = api.AnsatzSpec(n, layers, "cz")
+    C, g = api.vqls_grad_adjoint(an, _gpu(th), _gpu(coeffs), _gpu(strings), "local", "f64",
+                                 per_row_system=True)
+    for r in range(4):
+        At = rows[r][1]
+        parts = lambda t: oc.parts_theta_dense(t, At, n, layers, "cz", "local")
+        C0, g0 = oc.grad_parameter_shift(parts, th[r], n, "local")
+        assert abs(C[r].item() - C0) < 1e-12
+        assert np.max(np.abs(g[r].cpu().numpy() - g0)) < 1e-10
+
+
+def test_gradient_descent_trajectory_small_workload():
+    """n = 3 workload: 50 gradient-descent steps (eta = 0.1) with the
+    shift-rule gradient of the global cost; theta after every step within
+    1e-10 of the oracle's trajectory."""
+    n, layers, eta, steps = 3, 2, 0.1, 50
+    A, At, c, xs, zs, strings = _system(n, 1.0, -0.4, tau=0.01)
+    th0 = theta_uniform(n * layers, seed=0)
+    parts = lambda t: oc.parts_theta_dense(t, At, n, layers, "cz", "global")
+    want, wcost = oc.gradient_descent(th0, lambda t: oc.grad_parameter_shift(parts, t, n, "global"), eta, steps)
+    an = api.AnsatzSpec(n, layers, "cz")
+    theta = _gpu(th0.copy())
+    cg, sg = _gpu(c), _gpu(strings)
+    ws = api.ShiftWorkspace(an, len(c), "global", DEV)
+    for s in range(steps):
+        C, g = api.vqls_grad_shift(an, theta, cg, sg, "global", "f64", workspace=ws)
+        assert abs(C.item() - wcost[s]) < 1e-12
+        api.gd_step(theta, g, eta)
+        assert np.max(np.abs(theta.cpu().numpy() - want[s + 1])) < 1e-10, s
+
+
+def test_fidelity_matches_oracle():
+    n, layers = 6, 3
+    rng = np.random.default_rng(0)
+    th = rng.uniform(0, 2 * math.pi, size=(5, n * layers))
+    target = random_unit_vector(1 << n, seed=2, complex_=True)
+    an = api.AnsatzSpec(n, layers, "cnot")
+    F = api.fidelity(an, _gpu(th), _gpu(target)).cpu().numpy()
+    for r in range(5):
+        x = qc.ansatz_state(th[r], n, layers, "cnot")
+        assert abs(F[r] - ola.fidelity(x, target)) < 1e-13
+
+
+def test_adjoint_autograd_function():
+    n, layers = 3, 2
+    A, At, c, xs, zs, strings = _system(n, 1.0, -0.4, tau=0.01)
+    th = _gpu(theta_uniform(n * layers, seed=0)).requires_grad_(True)
+    an = api.AnsatzSpec(n, layers, "cz")
+    C = api.AdjointCost.apply(th, an, _gpu(c), _gpu(strings), "local", "f64", "plus", None)
+    (2.0 * C).backward()
+    parts = lambda t: oc.parts_theta_dense(t, At, n, layers, "cz", "local")
+    C0, g0 = oc.grad_parameter_shift(parts, th.detach().cpu().numpy(), n, "local")
+    assert abs(C.item() - C0) < 1e-12
+    assert np.max(np.abs(th.grad.cpu().numpy() - 2 * g0)) < 1e-10

@@ -1,0 +1,134 @@
+"""GPU parity: Hadamard-test circuit terms vs the oracle's gate-by-gate circuits.
+
+Bar (per term, absolute): 1e-12 for complex128 state vectors, 1e-5 for
+complex64 state vectors.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import circuit as qc
+from oracle import pauli as op
+from workloads import random_unit_vector, theta_uniform, toeplitz
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_2604_14435_amd import api  # noqa: E402
+
+DEV = "cuda:0"
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def _gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _system(n, a, b, tau=None, top_L=None):
+    C = op.decompose_fwht(toeplitz(n, a, b))
+    keep = op.select_tau(C, tau) if tau is not None else op.select_top(C, top_L)
+    c, xs, zs = op.kept_terms(C, keep)
+    strings = np.stack([xs, zs], axis=1).astype(np.int32)
+    return c, xs, zs, strings
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("exec_", ["literal", "generic"])
+@pytest.mark.parametrize("kind", ["global", "local"])
+def test_small_workload_all_terms(precision, exec_, kind):
+    """n = 3, tridiag(-0.4, 1, -0.4), tau = 0.01 -> L = 8; 2 layers RY + CZ;
+    theta ~ U[0, 2pi) from seed 0.  Every term of the evaluation."""
+    n, layers = 3, 2
+    c, xs, zs, strings = _system(n, 1.0, -0.4, tau=0.01)
+    assert len(xs) == 8
+    th = theta_uniform(n * layers, seed=0)
+    an = api.AnsatzSpec(n, layers, "cz")
+    beta, other = api.vqls_terms(an, _gpu(th), _gpu(strings), kind, precision, exec_=exec_)
+    wb, wo = qc.terms(th, n, layers, "cz", xs, zs, kind)
+    tol = TOL[precision]
+    assert np.max(np.abs(beta[0].cpu().numpy() - wb)) < tol
+    assert np.max(np.abs(other[0].cpu().numpy() - wo)) < tol
+
+
+@pytest.mark.parametrize("ent", ["cz", "cnot"])
+@pytest.mark.parametrize("b_kind", ["plus", "vector"])
+@pytest.mark.parametrize("kind", ["global", "local"])
+def test_entanglers_and_general_b(ent, b_kind, kind):
+    """Both ladders, |+> and a Householder-prepared real b, B = 3 rows, a
+    ragged L = 5 (strings with x = 0, odd Y counts and complex coefficients)."""
+    n, layers = 4, 2
+    rng = np.random.default_rng(3)
+    N = 1 << n
+    strings = np.array([[0, 0], [0, 5], [3, 1], [9, 9], [15, 6]], dtype=np.int32)
+    b = random_unit_vector(N, seed=5) if b_kind == "vector" else None
+    th = rng.uniform(0, 2 * math.pi, size=(3, n * layers))
+    an = api.AnsatzSpec(n, layers, ent)
+    for precision in ("f64", "f32"):
+        beta, other = api.vqls_terms(an, _gpu(th), _gpu(strings), kind, precision, b_kind,
+                                     None if b is None else _gpu(b))
+        for r in range(3):
+            wb, wo = qc.terms(th[r], n, layers, ent, strings[:, 0], strings[:, 1], kind, b_kind, b)
+            tol = TOL[precision]
+            assert np.max(np.abs(beta[r].cpu().numpy() - wb)) < tol, (precision, r)
+            assert np.max(np.abs(other[r].cpu().numpy() - wo)) < tol, (precision, r)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_n10_L64_sampled_circuits_and_invariants(precision):
+    """n = 10, tridiag(-0.45, 1, -0.45), tau = 0.01 -> L = 64, 4 layers: the full
+    evaluation (90,112 circuits) on the GPU; 40 sampled terms recomputed by the
+    oracle's circuits; invariants on every beta."""
+    n, layers = 10, 4
+    c, xs, zs, strings = _system(n, 1.0, -0.45, tau=0.01)
+    L_ = len(xs)
+    assert L_ == 64
+    th = theta_uniform(n * layers, seed=0)
+    an = api.AnsatzSpec(n, layers, "cz")
+    beta, delta = api.vqls_terms(an, _gpu(th), _gpu(strings), "local", precision)
+    beta = beta[0].cpu().numpy()
+    delta = delta[0].cpu().numpy()
+    tol = TOL[precision]
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        l, m = rng.integers(0, L_, 2)
+        want = qc.beta_term(th, n, layers, "cz", (int(xs[l]), int(zs[l])), (int(xs[m]), int(zs[m])))
+        assert abs(beta[l, m] - want) < tol
+    for _ in range(20):
+        j, l, m = int(rng.integers(0, n)), *rng.integers(0, L_, 2)
+        want = qc.delta_term(th, n, layers, "cz", (int(xs[l]), int(zs[l])), (int(xs[m]), int(zs[m])), j)
+        assert abs(delta[j, l, m] - want) < tol
+    assert np.max(np.abs(np.diag(beta) - 1.0)) < tol
+    assert np.max(np.abs(beta - beta.conj().T)) < 2 * tol
+    assert np.max(np.abs(beta.imag)) < tol
+    assert np.max(np.abs(beta)) < 1 + tol
+    for j in range(n):
+        assert np.max(np.abs(delta[j] - delta[j].conj().T)) < 2 * tol
+
+
+def test_theta_zero_by_hand_gpu():
+    """V(0)|0> = |0>: beta_lm = conj(i^{|x_l&z_l|}) i^{|x_m&z_m|} [x_l == x_m]."""
+    n, layers = 5, 3
+    rng = np.random.default_rng(4)
+    strings = rng.integers(0, 1 << n, size=(9, 2)).astype(np.int32)
+    strings[3, 0] = strings[1, 0]
+    an = api.AnsatzSpec(n, layers, "cz")
+    beta, _ = api.vqls_terms(an, _gpu(np.zeros(n * layers)), _gpu(strings), "global", "f64")
+    beta = beta[0].cpu().numpy()
+    for l in range(9):
+        for m in range(9):
+            pl = 1j ** bin(int(strings[l, 0] & strings[l, 1])).count("1")
+            pm = 1j ** bin(int(strings[m, 0] & strings[m, 1])).count("1")
+            want = np.conj(pl) * pm * (1.0 if strings[l, 0] == strings[m, 0] else 0.0)
+            assert abs(beta[l, m] - want) < 1e-14
+
+
+def test_bit_reproducible():
+    n, layers = 6, 3
+    c, xs, zs, strings = _system(n, 1.0, -0.45, top_L=16)
+    th = theta_uniform(n * layers, seed=2)
+    an = api.AnsatzSpec(n, layers, "cz")
+    for precision in ("f64", "f32"):
+        b1, o1 = api.vqls_terms(an, _gpu(th), _gpu(strings), "local", precision)
+        b2, o2 = api.vqls_terms(an, _gpu(th), _gpu(strings), "local", precision)
+        assert torch.equal(b1, b2) and torch.equal(o1, o2)
