@@ -225,3 +225,60 @@ def fidelity(ansatz: AnsatzSpec, theta: torch.Tensor, target: torch.Tensor) -> t
     a = ansatz.c()
     L.call("dvq_fidelity", ctypes.byref(a), _p(theta), theta.shape[0], _p(target), _p(F), _stream(theta))
     return F
+
+
+# -------------------------------------------------------------- warm-start MLP
+
+def mlp_shape(d_in: int, hidden: int, d_out: int) -> L.MlpShape:
+    return L.MlpShape(d_in, hidden, d_out)
+
+
+def mlp_param_count(shape: L.MlpShape) -> int:
+    return int(L.load().dvq_mlp_param_count(ctypes.byref(shape)))
+
+
+def mlp_forward(shape: L.MlpShape, params: torch.Tensor, X: torch.Tensor, out=None):
+    """(Y, H1, H2) float32; bfloat16 operands, float32 accumulation."""
+    params = _cuda(params, torch.float32, "params")
+    X = _cuda(X, torch.float32, "X")
+    B = X.shape[0]
+    if out is None:
+        H1 = torch.empty((B, shape.hidden), dtype=torch.float32, device=X.device)
+        H2 = torch.empty_like(H1)
+        Y = torch.empty((B, shape.d_out), dtype=torch.float32, device=X.device)
+    else:
+        Y, H1, H2 = out
+    L.call("dvq_mlp_forward", ctypes.byref(shape), _p(params), _p(X), B, _p(H1), _p(H2), _p(Y), _stream(X))
+    return Y, H1, H2
+
+
+def mlp_loss_grad(Y: torch.Tensor, T: torch.Tensor, out=None):
+    """(dY float32, loss float64 [1]) of mean(1 - cos(Y - T))."""
+    Y = _cuda(Y, torch.float32, "Y")
+    T = _cuda(T, torch.float32, "T")
+    if out is None:
+        dY = torch.empty_like(Y)
+        loss = torch.empty(1, dtype=torch.float64, device=Y.device)
+    else:
+        dY, loss = out
+    L.call("dvq_mlp_loss_grad", _p(Y), _p(T), Y.numel(), _p(dY), _p(loss), _stream(Y))
+    return dY, loss
+
+
+def mlp_backward(shape: L.MlpShape, params, X, H1, H2, dY, workspace=None, out=None):
+    """Parameter gradients, packed like params."""
+    B = X.shape[0]
+    lib = L.load()
+    if workspace is None:
+        workspace = torch.empty(lib.dvq_mlp_workspace_bytes(ctypes.byref(shape), B), dtype=torch.uint8,
+                                device=X.device)
+    dparams = torch.empty_like(params) if out is None else out
+    L.call("dvq_mlp_backward", ctypes.byref(shape), _p(params), _p(X), _p(H1), _p(H2), _p(dY), B,
+           _p(dparams), _p(workspace), workspace.numel(), _stream(X))
+    return dparams
+
+
+def adamw_step(params, grads, m, v, t: int, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+               eps: float = 1e-8, weight_decay: float = 0.0) -> None:
+    L.call("dvq_adamw_step", _p(params), _p(grads), _p(m), _p(v), params.numel(), int(t), float(lr),
+           float(beta1), float(beta2), float(eps), float(weight_decay), _stream(params))

@@ -66,6 +66,10 @@ __device__ __forceinline__ cplx<T> mul_ipow(cplx<T> a, int p) {
 
 __device__ __forceinline__ int parity(uint32_t v) { return __popc(v) & 1; }
 
+// Fused multiply-add in the operand's own precision.
+__device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // Block-wide sum of one double per thread; every thread gets the result.
 // Fixed reduction order (wavefront butterfly, then waves in index order), so
 // the result is bit-reproducible for a given block size.

@@ -6,12 +6,24 @@
 
 namespace dvq {
 
-constexpr int kCostThreads = 256;
+constexpr int kCostThreads = 1024;
 
-// One workgroup per theta row.  Psi = sum_lm conj(c_l) c_m beta_lm;
-// local: E = sum_j sum_lm conj(c_l) c_m delta^j_lm, C = 1/2 - Re[E/(n Psi)]/2;
-// global: G = |sum_l c_l gamma_l|^2, C = 1 - G/Psi.  Thread-strided partial
-// sums, then the fixed-order block reduction: bit-reproducible.
+// One workgroup per theta row sums the weighted terms (Section II-C stage ii,
+// weights w_lm = conj(c_l) c_m) and applies stage iii:
+//   Psi = sum_lm w_lm beta_lm;
+//   local:  E = sum_j sum_lm w_lm delta^j_lm, C = 1/2 - Re[E / (n Psi)] / 2;
+//   global: g = sum_l c_l gamma_l, G = |g|^2, C = 1 - G / Psi  (Eq. (1)).
+// Thread-strided partial sums, then the fixed-order block reduction, so the
+// result is bit-reproducible.
+__device__ __forceinline__ void acc_weighted(const dvq_c128* __restrict__ coeffs, int L, int64_t lm,
+                                             dvq_c128 t, double& ar, double& ai) {
+    const int l = (int)(lm / L), m = (int)(lm - (int64_t)l * L);
+    const dvq_c128 cl = coeffs[l], cm = coeffs[m];
+    const double wr = cl.re * cm.re + cl.im * cm.im, wi = cl.re * cm.im - cl.im * cm.re;
+    ar += wr * t.re - wi * t.im;
+    ai += wr * t.im + wi * t.re;
+}
+
 __global__ void __launch_bounds__(kCostThreads)
 k_cost(const dvq_c128* __restrict__ coeffs, int L, int n, int kind,
        const dvq_c128* __restrict__ beta, const dvq_c128* __restrict__ other,
@@ -21,37 +33,23 @@ k_cost(const dvq_c128* __restrict__ coeffs, int L, int n, int kind,
     const int64_t L2 = (int64_t)L * L;
     const dvq_c128* bt = beta + row * L2;
     double pr = 0.0, pi = 0.0;
-    for (int64_t i = threadIdx.x; i < L2; i += blockDim.x) {
-        const int l = (int)(i / L), m = (int)(i - (int64_t)l * L);
-        const dvq_c128 cl = coeffs[l], cm = coeffs[m], t = bt[i];
-        // w = conj(c_l) c_m
-        const double wr = cl.re * cm.re + cl.im * cm.im, wi = cl.re * cm.im - cl.im * cm.re;
-        pr += wr * t.re - wi * t.im;
-        pi += wr * t.im + wi * t.re;
-    }
+#pragma unroll 4
+    for (int64_t i = threadIdx.x; i < L2; i += kCostThreads) acc_weighted(coeffs, L, i, bt[i], pr, pi);
     pr = block_sum(pr, red);
     pi = block_sum(pi, red);
     double nr = 0.0, ni = 0.0, cost;
     if (kind == DVQ_COST_LOCAL) {
         const dvq_c128* dt = other + row * (int64_t)n * L2;
         const int64_t tot = (int64_t)n * L2;
-        for (int64_t i = threadIdx.x; i < tot; i += blockDim.x) {
-            const int64_t lm = i % L2;
-            const int l = (int)(lm / L), m = (int)(lm - (int64_t)l * L);
-            const dvq_c128 cl = coeffs[l], cm = coeffs[m], t = dt[i];
-            const double wr = cl.re * cm.re + cl.im * cm.im, wi = cl.re * cm.im - cl.im * cm.re;
-            nr += wr * t.re - wi * t.im;
-            ni += wr * t.im + wi * t.re;
-        }
+#pragma unroll 4
+        for (int64_t i = threadIdx.x; i < tot; i += kCostThreads) acc_weighted(coeffs, L, i % L2, dt[i], nr, ni);
         nr = block_sum(nr, red);
         ni = block_sum(ni, red);
-        // Re[E / (n Psi)]
-        const double den = n * (pr * pr + pi * pi);
-        cost = 0.5 - 0.5 * (nr * pr + ni * pi) / den;
+        cost = 0.5 - 0.5 * (nr * pr + ni * pi) / (n * (pr * pr + pi * pi));  // Re[E / (n Psi)]
     } else {
         const dvq_c128* gt = other + row * (int64_t)L;
         double gr = 0.0, gi = 0.0;
-        for (int l = threadIdx.x; l < L; l += blockDim.x) {
+        for (int l = threadIdx.x; l < L; l += kCostThreads) {
             const dvq_c128 cl = coeffs[l], t = gt[l];
             gr += cl.re * t.re - cl.im * t.im;
             gi += cl.re * t.im + cl.im * t.re;
@@ -60,8 +58,7 @@ k_cost(const dvq_c128* __restrict__ coeffs, int L, int n, int kind,
         gi = block_sum(gi, red);
         nr = gr * gr + gi * gi;
         ni = 0.0;
-        // 1 - Re[G / Psi]
-        cost = 1.0 - nr * pr / (pr * pr + pi * pi);
+        cost = 1.0 - nr * pr / (pr * pr + pi * pi);  // 1 - Re[G / Psi]
     }
     if (threadIdx.x == 0) {
         C[row] = cost;

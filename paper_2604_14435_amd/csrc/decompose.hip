@@ -267,12 +267,14 @@ k_partial_sq(const double* __restrict__ v, int64_t total, int mode, double tau, 
     if (threadIdx.x == 0) partials[blockIdx.x] = acc;
 }
 
-__global__ void k_sum_partials(const double* __restrict__ partials, int count, double* __restrict__ out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < count; ++i) s += partials[i];
-        *out = s;
-    }
+// Fixed-order sum of the partials (thread-strided, then the block tree).
+__global__ void __launch_bounds__(kDecThreads)
+k_sum_partials(const double* __restrict__ partials, int count, double* __restrict__ out) {
+    __shared__ double red[kDecThreads / 64];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < count; i += blockDim.x) s += partials[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) *out = s;
 }
 
 struct DecWs {
@@ -436,12 +438,12 @@ dvq_status dvq_pauli_decompose(const double* A, int32_t n, double tau, int64_t t
         hipLaunchKernelGGL(k_partial_sq, dim3(pb), dim3(kDecThreads), 0, s, w.values, total, mode, tau, thi,
                            tlo, w.partials);
         DVQ_CHECK_LAUNCH("k_partial_sq");
-        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, w.partials, pb, w.sums);
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kDecThreads), 0, s, w.partials, pb, w.sums);
         DVQ_CHECK_LAUNCH("k_sum_partials");
         hipLaunchKernelGGL(k_partial_sq, dim3(pb), dim3(kDecThreads), 0, s, A, total, 2, 0.0, 0ull, 0u,
                            w.partials);
         DVQ_CHECK_LAUNCH("k_partial_sq");
-        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, w.partials, pb, w.sums + 1);
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kDecThreads), 0, s, w.partials, pb, w.sums + 1);
         DVQ_CHECK_LAUNCH("k_sum_partials");
         double sums[2];
         DVQ_TRY_HIP(hipMemcpyAsync(sums, w.sums, sizeof(sums), hipMemcpyDeviceToHost, s));

@@ -1,0 +1,164 @@
+"""Learned warm start for the VQLS angles (a project form around the method).
+
+Pipeline, every arithmetic step in libdvq.so kernels (Python only orders the
+calls and moves tensors):
+  1. decompose each system of a family on the GPU (top-L Pauli terms);
+  2. generate training angles with the solver itself: gradient descent with
+     the adjoint gradient, all systems batched in one launch per iteration,
+     every system started from one common angle vector (the solution of a
+     reference system), so the optimised angles vary smoothly over the family;
+  3. train the bfloat16 MLP (descriptor -> angles) with the wrap-safe loss
+     mean(1 - cos(pred - target)) and AdamW;
+  4. predict initial angles for new systems; random initialisation remains
+     the reference and the fallback (a prediction whose cost is not finite or
+     is worse than the random start's is replaced by the random start).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import api
+
+
+def decompose_family(matrices, top_L: int, device) -> tuple[torch.Tensor, torch.Tensor, np.ndarray]:
+    """Top-L terms of each matrix: coeffs [S, L] complex128, strings [S, L, 2] int32,
+    relative Frobenius errors [S]."""
+    cs, ss, fe = [], [], []
+    for A in matrices:
+        c, s, f = api.pauli_decompose(torch.as_tensor(A, device=device), top_L=top_L)
+        cs.append(c)
+        ss.append(s)
+        fe.append(f)
+    return torch.stack(cs), torch.stack(ss), np.array(fe)
+
+
+def solve(ansatz: api.AnsatzSpec, coeffs, strings, theta0: torch.Tensor, iters: int, lr: float,
+          kind: str = "local", precision: str = "f32", per_row_system: bool = True,
+          record: bool = True):
+    """Gradient descent with the adjoint gradient for B rows at once.
+
+    Returns (theta [B, P], costs [iters + 1, B] or None); costs[t] is the cost
+    at the iterate after t steps."""
+    theta = theta0.clone().contiguous()
+    B = theta.shape[0]
+    C = torch.empty(B, dtype=torch.float64, device=theta.device)
+    g = torch.empty((B, ansatz.P), dtype=torch.float64, device=theta.device)
+    hist = torch.empty((iters + 1, B), dtype=torch.float64, device=theta.device) if record else None
+    for t in range(iters):
+        api.vqls_grad_adjoint(ansatz, theta, coeffs, strings, kind, precision,
+                              per_row_system=per_row_system, out=(C, g))
+        if record:
+            hist[t].copy_(C)
+        api.gd_step(theta, g, lr)
+    if record:
+        api.vqls_grad_adjoint(ansatz, theta, coeffs, strings, kind, precision,
+                              per_row_system=per_row_system, out=(C, g))
+        hist[iters].copy_(C)
+    return theta, hist
+
+
+def iterations_to(costs: torch.Tensor, threshold: torch.Tensor) -> torch.Tensor:
+    """First iteration index t with costs[t, b] <= threshold[b]; -1 if never."""
+    hit = costs <= threshold.unsqueeze(0)
+    idx = torch.where(hit.any(0), hit.float().argmax(0), torch.full_like(hit[0], -1, dtype=torch.long))
+    return idx.long()
+
+
+@dataclass
+class MLPConfig:
+    hidden: int = 256
+    epochs: int = 300
+    batch: int = 256
+    lr: float = 1e-3
+    weight_decay: float = 0.0
+    seed: int = 0
+
+
+class WarmStartMLP:
+    """d_in -> hidden -> hidden -> P network on the bfloat16 matrix cores."""
+
+    def __init__(self, d_in: int, d_out: int, cfg: MLPConfig = MLPConfig(), device="cuda:0"):
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.shape = api.mlp_shape(d_in, cfg.hidden, d_out)
+        self.params = self.init_params(d_in, cfg.hidden, d_out, cfg.seed).to(self.device)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grads = torch.empty_like(self.params)
+        self.t = 0
+        self.mu = torch.zeros(d_in, dtype=torch.float32, device=self.device)
+        self.sd = torch.ones(d_in, dtype=torch.float32, device=self.device)
+
+    @staticmethod
+    def init_params(d_in: int, hidden: int, d_out: int, seed: int) -> torch.Tensor:
+        """He-uniform weights, zero biases, packed W1, b1, W2, b2, W3, b3."""
+        rng = np.random.default_rng(seed)
+
+        def w(o, i):
+            lim = math.sqrt(6.0 / i)
+            return rng.uniform(-lim, lim, size=(o, i)).astype(np.float32).ravel()
+
+        z = lambda k: np.zeros(k, dtype=np.float32)
+        flat = np.concatenate([w(hidden, d_in), z(hidden), w(hidden, hidden), z(hidden),
+                               w(d_out, hidden), z(d_out)])
+        return torch.from_numpy(flat)
+
+    def _features(self, X) -> torch.Tensor:
+        X = torch.as_tensor(X, dtype=torch.float32, device=self.device)
+        return ((X - self.mu) / self.sd).contiguous()
+
+    def fit(self, X, T, epochs: int | None = None):
+        """Train on descriptors X [S, d_in] and angles T [S, P]; returns the
+        per-epoch mean loss (float64 numpy)."""
+        cfg = self.cfg
+        X = torch.as_tensor(X, dtype=torch.float32, device=self.device)
+        self.mu = X.mean(0)
+        self.sd = X.std(0).clamp_min(1e-12)
+        Xf = self._features(X)
+        T = torch.as_tensor(T, dtype=torch.float32, device=self.device).contiguous()
+        S = Xf.shape[0]
+        bs = min(cfg.batch, S)
+        gen = torch.Generator().manual_seed(cfg.seed)
+        ws = None
+        losses = []
+        for _ in range(epochs if epochs is not None else cfg.epochs):
+            perm = torch.randperm(S, generator=gen).to(self.device)
+            tot = torch.zeros(1, dtype=torch.float64, device=self.device)
+            nb = 0
+            for s0 in range(0, S - bs + 1, bs):
+                idx = perm[s0:s0 + bs]
+                xb, tb = Xf[idx].contiguous(), T[idx].contiguous()
+                Y, H1, H2 = api.mlp_forward(self.shape, self.params, xb)
+                dY, loss = api.mlp_loss_grad(Y, tb)
+                if ws is None:
+                    import ctypes
+                    from . import _lib
+                    ws = torch.empty(_lib.load().dvq_mlp_workspace_bytes(ctypes.byref(self.shape), bs),
+                                     dtype=torch.uint8, device=self.device)
+                api.mlp_backward(self.shape, self.params, xb, H1, H2, dY, ws, out=self.grads)
+                self.t += 1
+                api.adamw_step(self.params, self.grads, self.m, self.v, self.t, cfg.lr,
+                               weight_decay=cfg.weight_decay)
+                tot += loss
+                nb += 1
+            losses.append(tot / max(nb, 1))
+        return torch.cat(losses).cpu().numpy()
+
+    def predict(self, X) -> torch.Tensor:
+        """Initial angles [S, P] as float64."""
+        Y, _, _ = api.mlp_forward(self.shape, self.params, self._features(X))
+        return Y.double()
+
+
+def choose_start(ansatz, coeffs, strings, theta_pred, theta_rand, kind="local", precision="f32"):
+    """Fallback rule: keep the predicted start where its cost is finite and not
+    worse than the random start's, else use the random start.  Returns
+    (theta0 [S, P], used_prediction bool [S])."""
+    Cp, _ = api.vqls_grad_adjoint(ansatz, theta_pred, coeffs, strings, kind, precision, per_row_system=True)
+    Cr, _ = api.vqls_grad_adjoint(ansatz, theta_rand, coeffs, strings, kind, precision, per_row_system=True)
+    use = torch.isfinite(Cp) & (Cp <= Cr)
+    return torch.where(use.unsqueeze(1), theta_pred, theta_rand), use

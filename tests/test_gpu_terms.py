@@ -132,3 +132,32 @@ def test_bit_reproducible():
         b1, o1 = api.vqls_terms(an, _gpu(th), _gpu(strings), "local", precision)
         b2, o2 = api.vqls_terms(an, _gpu(th), _gpu(strings), "local", precision)
         assert torch.equal(b1, b2) and torch.equal(o1, o2)
+
+
+@pytest.mark.parametrize("n,layers,precision", [(10, 1, "f32"), (10, 3, "f64"), (10, 5, "f32"),
+                                                (10, 6, "f64"), (11, 2, "f32"), (11, 3, "f32")])
+def test_wavefront_kernel_shapes(n, layers, precision):
+    """The register-resident kernel (n = 10, 11): even and odd layer counts,
+    a ragged L = 7 with x = 0 strings, odd Y counts and every j; sampled
+    terms against the oracle's circuits, and the full output against the
+    generic LDS kernel."""
+    rng = np.random.default_rng(n * 10 + layers)
+    N = 1 << n
+    strings = rng.integers(0, N, size=(7, 2)).astype(np.int32)
+    strings[0] = (0, 0)
+    strings[1, 0] = 0
+    th = rng.uniform(0, 2 * math.pi, size=(2, n * layers))
+    an = api.AnsatzSpec(n, layers, "cz")
+    beta, delta = api.vqls_terms(an, _gpu(th), _gpu(strings), "local", precision)
+    gb, gd = api.vqls_terms(an, _gpu(th), _gpu(strings), "local", precision, exec_="generic")
+    tol = TOL[precision]
+    assert torch.max(torch.abs(beta - gb)).item() < 2 * tol
+    assert torch.max(torch.abs(delta - gd)).item() < 2 * tol
+    beta, delta = beta.cpu().numpy(), delta.cpu().numpy()
+    for r in range(2):
+        for _ in range(4):
+            l, m = (int(v) for v in rng.integers(0, 7, 2))
+            sl, sm = (int(strings[l, 0]), int(strings[l, 1])), (int(strings[m, 0]), int(strings[m, 1]))
+            assert abs(beta[r, l, m] - qc.beta_term(th[r], n, layers, "cz", sl, sm)) < tol
+            j = int(rng.integers(0, n))
+            assert abs(delta[r, j, l, m] - qc.delta_term(th[r], n, layers, "cz", sl, sm, j)) < tol
