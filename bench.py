@@ -87,6 +87,9 @@ def main() -> int:
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="run one device copy of this many MiB first (calibrates HBM counters)")
+    ap.add_argument("--no-fwht", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -101,6 +104,12 @@ def main() -> int:
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     n, layers = N_QUBITS, LAYERS
     an = api.AnsatzSpec(n, layers, "cz")
     P = an.P
@@ -169,6 +178,39 @@ def main() -> int:
     plain_s = (time.perf_counter() - t0) / args.plain_steps
     plain_circuits = (2 * P + 1) * circuits
 
+    # the prefix-shared execution of the same evaluation (reported separately)
+    api.vqls_terms(an, theta0, strings, "local", "f32", exec_="shared", out=(beta, delta))
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        api.vqls_terms(an, theta0, strings, "local", "f32", exec_="shared", out=(beta, delta))
+    e1.record()
+    torch.cuda.synchronize()
+    shared_ms = e0.elapsed_time(e1) / args.steps
+
+    # FWHT decomposition of the dense random symmetric 4096 x 4096 matrix
+    fwht = None
+    if not args.no_fwht:
+        from workloads import random_symmetric
+        A12 = torch.from_numpy(random_symmetric(12, seed=0)).to(dev)
+        c12 = api.pauli_decompose_dense(A12)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record()
+        for _ in range(reps):
+            api.pauli_decompose_dense(A12)
+        e1.record()
+        torch.cuda.synchronize()
+        fwht_ms = e0.elapsed_time(e1) / reps
+        alg_bytes = (8 + 16) * 4 ** 12
+        fwht = {"bound": "hbm", "achieved": round(alg_bytes / (fwht_ms * 1e-3) / 1e9, 1), "peak": 8000.0,
+                "unit": "GB/s", "frac": round(alg_bytes / (fwht_ms * 1e-3) / 8e12, 4), "traffic": None,
+                "kernel": "k_fwht_pass1 + k_fwht_pass2 (n=12 dense)", "avg_ms": round(fwht_ms, 4),
+                "algorithmic_bytes": alg_bytes}
+        del A12, c12
+
     # float32 form vs the float64 path at theta0 (terms, cost, gradient)
     b32, d32 = api.vqls_terms(an, theta0, strings, "local", "f32")
     b64, d64 = api.vqls_terms(an, theta0, strings, "local", "f64")
@@ -215,6 +257,10 @@ def main() -> int:
         "frobenius_error": round(ferr, 6),
         "error_fp32_vs_fp64": errors,
         "roofline": roofline,
+        "prefix_shared": {"terms_ms": round(shared_ms, 4),
+                          "circuits_per_s": round(circuits / (shared_ms * 1e-3), 1),
+                          "note": "same circuits and results; the ansatz prefix simulated once per wavefront"},
+        "roofline_fwht": fwht,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

@@ -79,7 +79,7 @@ enum { DVQ_COST_GLOBAL = 0, DVQ_COST_LOCAL = 1 };
 enum { DVQ_ENT_CZ_LADDER = 0, DVQ_ENT_CNOT_LADDER = 1 };
 enum { DVQ_F64 = 0, DVQ_F32 = 1 };
 enum { DVQ_B_PLUS = 0, DVQ_B_VECTOR = 1 };
-enum { DVQ_EXEC_LITERAL = 0, DVQ_EXEC_GENERIC = 1 };
+enum { DVQ_EXEC_LITERAL = 0, DVQ_EXEC_GENERIC = 1, DVQ_EXEC_SHARED = 2 };
 
 typedef struct {
     int32_t n;         /* system qubits, 1..12 (circuits use n + 1 qubits)  */
@@ -160,7 +160,12 @@ int64_t dvq_circuit_count(int32_t n, int32_t L, int32_t cost_kind);
  *             circuit, amplitudes in registers) where available, else the
  *             generic kernel; DVQ_EXEC_GENERIC: always the generic kernel
  *             (one workgroup per circuit, amplitudes in LDS, one pass per
- *             gate).
+ *             gate); DVQ_EXEC_SHARED: the prefix common to every circuit
+ *             of a row (ancilla H and V(theta)) is simulated once per
+ *             wavefront and each circuit's own gates (controlled strings,
+ *             X_j, S^dagger, H, measurement) are applied to a copy of that
+ *             state -- the same results; shapes without a shared kernel fall
+ *             back to the generic kernel.
  * Limits: n <= 12 (F64) / 13 (F32); B * circuits < 2^31.
  */
 dvq_status dvq_vqls_terms(const dvq_ansatz* ansatz, const double* theta, int32_t B,

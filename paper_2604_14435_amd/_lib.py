@@ -32,7 +32,7 @@ DVQ_COST_GLOBAL, DVQ_COST_LOCAL = 0, 1
 DVQ_ENT_CZ_LADDER, DVQ_ENT_CNOT_LADDER = 0, 1
 DVQ_F64, DVQ_F32 = 0, 1
 DVQ_B_PLUS, DVQ_B_VECTOR = 0, 1
-DVQ_EXEC_LITERAL, DVQ_EXEC_GENERIC = 0, 1
+DVQ_EXEC_LITERAL, DVQ_EXEC_GENERIC, DVQ_EXEC_SHARED = 0, 1, 2
 
 _A = POINTER(Ansatz)
 _M = POINTER(MlpShape)

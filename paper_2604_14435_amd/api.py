@@ -16,7 +16,7 @@ from . import _lib as L
 ENTANGLERS = {"cz": L.DVQ_ENT_CZ_LADDER, "cnot": L.DVQ_ENT_CNOT_LADDER}
 KINDS = {"global": L.DVQ_COST_GLOBAL, "local": L.DVQ_COST_LOCAL}
 PRECISIONS = {"f64": L.DVQ_F64, "f32": L.DVQ_F32}
-EXECS = {"literal": L.DVQ_EXEC_LITERAL, "generic": L.DVQ_EXEC_GENERIC}
+EXECS = {"literal": L.DVQ_EXEC_LITERAL, "generic": L.DVQ_EXEC_GENERIC, "shared": L.DVQ_EXEC_SHARED}
 
 
 @dataclass(frozen=True)

@@ -29,6 +29,7 @@ SOURCES = [
     "circuits_fast.hip",
     "cost.hip",
     "adjoint.hip",
+    "adjoint_fast.hip",
     "mlp.hip",
 ]
 

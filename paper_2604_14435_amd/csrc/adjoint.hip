@@ -207,6 +207,9 @@ extern "C" dvq_status dvq_vqls_grad_adjoint(const dvq_ansatz* ansatz, const doub
     DVQ_REQUIRE(cost_kind == DVQ_COST_GLOBAL || cost_kind == DVQ_COST_LOCAL, "unknown cost kind");
     DVQ_REQUIRE(precision == DVQ_F32 || precision == DVQ_F64, "unknown precision %d", precision);
     hipStream_t s = stream_of(stream);
+    st = launch_adjoint_fast(ansatz, theta, B, precision, coeffs, strings, L, per_row_system, b_kind, b,
+                             cost_kind, C, grad, s);
+    if (st != DVQ_EUNSUPPORTED) return st;
     return precision == DVQ_F32
                ? launch_adjoint<float>(ansatz, theta, B, coeffs, strings, L, per_row_system, b_kind,
                                        b, cost_kind, C, grad, s)

@@ -1,0 +1,370 @@
+// Adjoint gradient with the state in registers: one wavefront per parameter
+// row (n = 10, 11; CZ ladder).  Same mathematics as k_adjoint (adjoint.hip):
+//   x = V(theta)|0>, y = A x (A = sum_l c_l P_l), Psi = <y|y>,
+//   local:  u = U_b^dag y, E = sum_k |u_k|^2 (n - 2|k|),
+//           v = dC/dE * U_b D u + dC/dPsi * y   (D = diag(n - 2|k|) = sum_j Z_j);
+//   global: g = <b|y>, v = dC/dG * g b + dC/dPsi * y;
+//   lambda = A^dag v; then the gates are undone on x and lambda together and
+//   every RY gives dC/dtheta_k = Re <K_q x_k | lambda_k>.
+// The two vectors of the reverse sweep share the registers of one wavefront:
+// lanes 0..31 hold x, lanes 32..63 hold lambda (the "half" bit of the
+// layouts in wave_state.h), so every undo step is one pass over the
+// registers; the inner products pair each lane with lane +- 32 through
+// v_permlane32_swap.  Within a layer the RYs commute, so the gradient of each
+// RY may be taken before or after undoing the others of the same layer.
+// The Pauli sums and U_b are computed on natural-order copies in LDS.
+#include "wave_state.h"
+
+namespace dvq {
+
+__device__ __forceinline__ float other_half(float x) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float((threadIdx.x & 32) ? r[0] : r[1]);
+}
+
+__device__ __forceinline__ double other_half(double x) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
+    const auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    const bool up = threadIdx.x & 32;
+    const unsigned nlo = up ? rl[0] : rl[1], nhi = up ? rh[0] : rh[1];
+    return __longlong_as_double((long long)(((unsigned long long)nhi << 32) | nlo));
+}
+
+// Re <K_q x | lambda> summed over this lane's pairs of qubit Q, with the
+// lazy-ladder sign when PAR; meaningful in lanes 0..31 (0 in the others).
+template <typename T, int NQ, bool HI, int Q, int PAR>
+__device__ __forceinline__ double grad_reg(const T* re, const T* im, int lane) {
+    using Ly = Lay<NQ, HI>;
+    constexpr int R = Ly::R;
+    constexpr int j = Ly::reg(Q);
+    double acc = 0.0;
+#pragma unroll
+    for (int r0 = 0; r0 < R; ++r0) {
+        if (r0 & (1 << j)) continue;
+        const int r1 = r0 | (1 << j);
+        const T l0r = other_half(re[r0]), l0i = other_half(im[r0]);
+        const T l1r = other_half(re[r1]), l1i = other_half(im[r1]);
+        // (K x)[i0] = -x[i1], (K x)[i1] = x[i0]
+        const T v = (re[r0] * l1r + im[r0] * l1i) - (re[r1] * l0r + im[r1] * l0i);
+        const bool neg = PAR ? reg_rho<NQ, HI, Q>(r0) : false;
+        acc += neg ? -(double)v : (double)v;
+    }
+    if (PAR && lane_rho<NQ, HI, Q>(lane)) acc = -acc;
+    return (lane & 32) ? 0.0 : acc;
+}
+
+// For every register qubit q in [Q, QEND): gradient of RY_q, then undo RY_q.
+template <typename T, int NQ, bool HI, int PAR, int Q, int QEND>
+__device__ __forceinline__ void grad_undo_range(T* re, T* im, int lane, const T* trig, int kbase,
+                                                double* __restrict__ grad) {
+    if constexpr (Q < QEND) {
+        if constexpr (Lay<NQ, HI>::reg(Q) >= 0) {
+            const double gq = wave_sum(grad_reg<T, NQ, HI, Q, PAR>(re, im, lane));
+            if (lane == 0) grad[kbase + Q] = gq;
+            const T t = -trig[2 * (kbase + Q)], s = -trig[2 * (kbase + Q) + 1];
+            ry_reg<T, NQ, HI, Q, PAR>(re, im, lane, t, s);
+        }
+        grad_undo_range<T, NQ, HI, PAR, Q + 1, QEND>(re, im, lane, trig, kbase, grad);
+    }
+}
+
+// H on every register qubit q in [Q, QEND).
+template <typename T, int NQ, bool HI, int Q, int QEND>
+__device__ __forceinline__ void h_range(T* re, T* im) {
+    if constexpr (Q < QEND) {
+        constexpr int j = Lay<NQ, HI>::reg(Q);
+        if constexpr (j >= 0) {
+            constexpr int R = Lay<NQ, HI>::R;
+            const T r2 = (T)0.70710678118654752440;
+#pragma unroll
+            for (int r0 = 0; r0 < R; ++r0) {
+                if (r0 & (1 << j)) continue;
+                const int r1 = r0 | (1 << j);
+                const T ar = re[r0], ai = im[r0], br = re[r1], bi = im[r1];
+                re[r0] = (ar + br) * r2;
+                im[r0] = (ai + bi) * r2;
+                re[r1] = (ar - br) * r2;
+                im[r1] = (ai - bi) * r2;
+            }
+        }
+        h_range<T, NQ, HI, Q + 1, QEND>(re, im);
+    }
+}
+
+// Load both halves from natural-order LDS regions (lanes 0..31 from S0,
+// lanes 32..63 from S1) into layout HI / LO, applying S^p.
+template <typename T, int NQ, bool HI>
+__device__ __forceinline__ void load_halves(T* re, T* im, const cplx<T>* S0, const cplx<T>* S1, int lane,
+                                            int p) {
+    constexpr int R = Lay<NQ, HI>::R;
+    constexpr int N = 1 << NQ;
+    const cplx<T>* src = (lane & 32) ? S1 : S0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int g = Lay<NQ, HI>::g(lane, r) & (N - 1);
+        const cplx<T> v = src[pad_slot(g)];
+        const bool flip = p && ladder_flip<NQ>(g);
+        re[r] = flip ? -v.re : v.re;
+        im[r] = flip ? -v.im : v.im;
+    }
+    __syncthreads();
+}
+
+// Store lanes 0..31 (half 0) into a natural-order region, applying S^p.
+template <typename T, int NQ, bool HI>
+__device__ __forceinline__ void store_half0(const T* re, const T* im, cplx<T>* S0, int lane, int p) {
+    constexpr int R = Lay<NQ, HI>::R;
+    if (!(lane & 32)) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int g = Lay<NQ, HI>::g(lane, r);
+            const bool flip = p && ladder_flip<NQ>(g);
+            S0[pad_slot(g)] = flip ? cplx<T>{-re[r], -im[r]} : cplx<T>{re[r], im[r]};
+        }
+    }
+    __syncthreads();
+}
+
+// out[k] = sum_l w_l (P_l in)[k] over natural-order regions, w_l = c_l or conj(c_l).
+template <typename T, int NQ>
+__device__ __forceinline__ void wave_pauli_sum(cplx<T>* out, const cplx<T>* in, const dvq_pauli* sp,
+                                               const dvq_c128* cp, int L, bool conj_c, int lane) {
+    constexpr int N = 1 << NQ;
+    for (int i = 0; i < N / 64; ++i) {
+        const int k = lane + 64 * i;
+        T ar = 0, ai = 0;
+        for (int l = 0; l < L; ++l) {
+            const uint32_t x = sp[l].x, z = sp[l].z;
+            const int kk = k ^ (int)x;
+            const cplx<T> v = mul_ipow(in[pad_slot(kk)], (int)__popc(x & z) + 2 * parity(z & (uint32_t)kk));
+            const T cr = (T)cp[l].re, ci = conj_c ? -(T)cp[l].im : (T)cp[l].im;
+            ar += cr * v.re - ci * v.im;
+            ai += cr * v.im + ci * v.re;
+        }
+        out[pad_slot(k)] = {ar, ai};
+    }
+    __syncthreads();
+}
+
+// Householder U_b (= U_b^dagger) applied to a natural-order region in place.
+template <typename T, int NQ>
+__device__ __forceinline__ void wave_householder(cplx<T>* v, const double* __restrict__ b, int lane) {
+    constexpr int N = 1 << NQ;
+    const double s = (b[0] > 0.0) ? -1.0 : 1.0;
+    double ww = 0.0, dr = 0.0, di = 0.0;
+    for (int k = lane; k < N; k += 64) {
+        const double w = (k == 0 ? 1.0 : 0.0) - s * b[k];
+        const cplx<T> a = v[pad_slot(k)];
+        ww += w * w;
+        dr += w * (double)a.re;
+        di += w * (double)a.im;
+    }
+    ww = wave_sum(ww);
+    dr = wave_sum(dr);
+    di = wave_sum(di);
+    const double fr = 2.0 * dr / ww, fi = 2.0 * di / ww;
+    __syncthreads();
+    for (int k = lane; k < N; k += 64) {
+        const double w = (k == 0 ? 1.0 : 0.0) - s * b[k];
+        const cplx<T> a = v[pad_slot(k)];
+        v[pad_slot(k)] = {(T)(s * ((double)a.re - w * fr)), (T)(s * ((double)a.im - w * fi))};
+    }
+    __syncthreads();
+}
+
+template <typename T, int NQ>
+__host__ __device__ constexpr size_t wave_adjoint_lds(int layers, int L) {
+    constexpr int N = 1 << NQ;
+    return (size_t)(2 * N + (2 * N) / 32) * sizeof(cplx<T>)      // scratch for layout swaps
+           + 3 * (size_t)(N + N / 32) * sizeof(cplx<T>)          // x, y/lambda, v
+           + (size_t)L * (sizeof(dvq_pauli) + sizeof(dvq_c128))  // strings, coeffs
+           + (size_t)2 * NQ * layers * sizeof(T);                // rotation table
+}
+
+template <typename T, int NQ>
+__global__ void __launch_bounds__(64)
+k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __restrict__ coeffs,
+               const dvq_pauli* __restrict__ strings, int L, int per_row_system, int bkind,
+               const double* __restrict__ bvec, int kind, double* __restrict__ Cout,
+               double* __restrict__ grad) {
+    constexpr int N = 1 << NQ;
+    constexpr int R = Lay<NQ, false>::R;
+    constexpr int N1 = N + N / 32;
+    extern __shared__ __align__(16) unsigned char smem[];
+    cplx<T>* S = reinterpret_cast<cplx<T>*>(smem);
+    cplx<T>* RX = S + (2 * N + (2 * N) / 32);
+    cplx<T>* RY = RX + N1;
+    cplx<T>* RV = RY + N1;
+    dvq_pauli* sp = reinterpret_cast<dvq_pauli*>(RV + N1);
+    dvq_c128* cp = reinterpret_cast<dvq_c128*>(sp + L);
+    T* trig = reinterpret_cast<T*>(cp + L);
+    const int lane = threadIdx.x;
+    const int64_t row = blockIdx.x;
+    const int P = NQ * layers;
+    const int64_t sys = per_row_system ? row * L : 0;
+    for (int l = lane; l < L; l += 64) {
+        sp[l] = strings[sys + l];
+        cp[l] = coeffs[sys + l];
+    }
+    rotation_table<T>(theta + row * P, P, trig, lane);  // ends with a barrier
+
+    // forward: both halves start in |0> and evolve identically
+    T re[R], im[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        re[r] = (r == 0 && (lane & 31) == 0) ? (T)1 : (T)0;
+        im[r] = (T)0;
+    }
+    forward_layers<T, NQ>(re, im, S, trig, layers, lane);
+    const int pf = layers & 1;
+    if (pf)
+        store_half0<T, NQ, true>(re, im, RX, lane, 1);
+    else
+        store_half0<T, NQ, false>(re, im, RX, lane, 0);
+
+    // y = A x, Psi = <y|y>
+    wave_pauli_sum<T, NQ>(RY, RX, sp, cp, L, false, lane);
+    double ps = 0.0;
+    for (int k = lane; k < N; k += 64) {
+        const cplx<T> a = RY[pad_slot(k)];
+        ps += (double)a.re * a.re + (double)a.im * a.im;
+    }
+    const double Psi = wave_sum(ps);
+
+    double cost;
+    if (kind == DVQ_COST_LOCAL) {
+        double aE, aPsi;
+        if (bkind == DVQ_B_PLUS) {
+            // u = H^n y in registers (LO -> HI), E, D u, H^n again (HI -> LO)
+            load_halves<T, NQ, false>(re, im, RY, RY, lane, 0);
+            h_range<T, NQ, false, 0, NQ>(re, im);
+            relayout<T, NQ, false>(re, im, S, lane);
+            h_range<T, NQ, true, Lay<NQ, false>::RB, NQ>(re, im);
+            double es = 0.0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int g = Lay<NQ, true>::g(lane, r);
+                const T d = (T)(NQ - 2 * (int)__popc((unsigned)(g & (N - 1))));
+                if (!(lane & 32)) es += ((double)re[r] * re[r] + (double)im[r] * im[r]) * (double)d;
+                re[r] *= d;
+                im[r] *= d;
+            }
+            const double E = wave_sum(es);
+            cost = 0.5 - 0.5 * E / (NQ * Psi);
+            aE = -0.5 / (NQ * Psi);
+            aPsi = 0.5 * E / (NQ * Psi * Psi);
+            h_range<T, NQ, true, Lay<NQ, false>::RB, NQ>(re, im);
+            relayout<T, NQ, true>(re, im, S, lane);
+            h_range<T, NQ, false, 0, NQ>(re, im);
+            store_half0<T, NQ, false>(re, im, RV, lane, 0);
+        } else {
+            for (int k = lane; k < N; k += 64) RV[pad_slot(k)] = RY[pad_slot(k)];
+            __syncthreads();
+            wave_householder<T, NQ>(RV, bvec, lane);
+            double es = 0.0;
+            for (int k = lane; k < N; k += 64) {
+                const cplx<T> a = RV[pad_slot(k)];
+                const T d = (T)(NQ - 2 * (int)__popc((unsigned)k));
+                es += ((double)a.re * a.re + (double)a.im * a.im) * (double)d;
+                RV[pad_slot(k)] = {a.re * d, a.im * d};
+            }
+            const double E = wave_sum(es);
+            __syncthreads();
+            cost = 0.5 - 0.5 * E / (NQ * Psi);
+            aE = -0.5 / (NQ * Psi);
+            aPsi = 0.5 * E / (NQ * Psi * Psi);
+            wave_householder<T, NQ>(RV, bvec, lane);
+        }
+        for (int k = lane; k < N; k += 64) {
+            const cplx<T> w = RV[pad_slot(k)], y = RY[pad_slot(k)];
+            RV[pad_slot(k)] = {(T)(aE * w.re + aPsi * y.re), (T)(aE * w.im + aPsi * y.im)};
+        }
+        __syncthreads();
+    } else {
+        const double invs = 1.0 / sqrt((double)N);
+        double gr = 0.0, gi = 0.0;
+        for (int k = lane; k < N; k += 64) {
+            const double bk = bkind == DVQ_B_PLUS ? invs : bvec[k];
+            const cplx<T> y = RY[pad_slot(k)];
+            gr += bk * y.re;
+            gi += bk * y.im;
+        }
+        gr = wave_sum(gr);
+        gi = wave_sum(gi);
+        const double G = gr * gr + gi * gi;
+        cost = 1.0 - G / Psi;
+        const double aG = -1.0 / Psi, aPsi = G / (Psi * Psi);
+        for (int k = lane; k < N; k += 64) {
+            const double bk = bkind == DVQ_B_PLUS ? invs : bvec[k];
+            const cplx<T> y = RY[pad_slot(k)];
+            RV[pad_slot(k)] = {(T)(aG * gr * bk + aPsi * y.re), (T)(aG * gi * bk + aPsi * y.im)};
+        }
+        __syncthreads();
+    }
+    // lambda = A^dag v -> RY
+    wave_pauli_sum<T, NQ>(RY, RV, sp, cp, L, true, lane);
+
+    // reverse sweep: x in lanes 0..31, lambda in lanes 32..63
+    double* g = grad + row * P;
+    int l = layers - 1;
+    if (pf) {
+        // last layer even-indexed: ended in HI with p = 1 after its ladder
+        load_halves<T, NQ, true>(re, im, RX, RY, lane, 1);
+        grad_undo_range<T, NQ, true, 0, Lay<NQ, false>::RB, NQ>(re, im, lane, trig, l * NQ, g);
+        relayout<T, NQ, true>(re, im, S, lane);
+        grad_undo_range<T, NQ, false, 0, 0, NQ>(re, im, lane, trig, l * NQ, g);
+        --l;
+    } else {
+        load_halves<T, NQ, false>(re, im, RX, RY, lane, 0);
+    }
+    for (; l >= 1; l -= 2) {
+        // odd layer l (p = 1 during its RYs): LO qubits 0..4, swap, HI qubits
+        grad_undo_range<T, NQ, false, 1, 0, 5>(re, im, lane, trig, l * NQ, g);
+        relayout<T, NQ, false>(re, im, S, lane);
+        grad_undo_range<T, NQ, true, 1, 0, NQ>(re, im, lane, trig, l * NQ, g);
+        // even layer l - 1 (p = 0): HI qubits RB..NQ-1, swap, LO qubits
+        grad_undo_range<T, NQ, true, 0, Lay<NQ, false>::RB, NQ>(re, im, lane, trig, (l - 1) * NQ, g);
+        relayout<T, NQ, true>(re, im, S, lane);
+        grad_undo_range<T, NQ, false, 0, 0, NQ>(re, im, lane, trig, (l - 1) * NQ, g);
+    }
+    if (lane == 0) Cout[row] = cost;
+}
+
+template <typename T, int NQ>
+static dvq_status launch_adjoint_wave(const dvq_ansatz* an, const double* theta, int B,
+                                      const dvq_c128* coeffs, const dvq_pauli* strings, int L,
+                                      int per_row_system, int bkind, const double* b, int kind,
+                                      double* C, double* grad, hipStream_t s) {
+    const size_t lds = wave_adjoint_lds<T, NQ>(an->layers, L);
+    if (lds > kMaxLdsBytes) return DVQ_EUNSUPPORTED;
+    DVQ_TRY_HIP(allow_lds((const void*)k_adjoint_wave<T, NQ>, lds));
+    hipLaunchKernelGGL((k_adjoint_wave<T, NQ>), dim3(B), dim3(64), lds, s, theta, an->layers, coeffs,
+                       strings, L, per_row_system, bkind, b, kind, C, grad);
+    DVQ_CHECK_LAUNCH("k_adjoint_wave");
+    return DVQ_OK;
+}
+
+// Dispatch for the register-resident adjoint; DVQ_EUNSUPPORTED when the
+// shape has no such kernel (the LDS kernel then runs).
+dvq_status launch_adjoint_fast(const dvq_ansatz* an, const double* theta, int B, int precision,
+                               const dvq_c128* coeffs, const dvq_pauli* strings, int L,
+                               int per_row_system, int bkind, const double* b, int kind, double* C,
+                               double* grad, hipStream_t s) {
+    if (an->entangler != DVQ_ENT_CZ_LADDER || an->n * an->layers > 1024) return DVQ_EUNSUPPORTED;
+    if (precision == DVQ_F32) {
+        if (an->n == 10)
+            return launch_adjoint_wave<float, 10>(an, theta, B, coeffs, strings, L, per_row_system, bkind, b,
+                                                  kind, C, grad, s);
+        if (an->n == 11)
+            return launch_adjoint_wave<float, 11>(an, theta, B, coeffs, strings, L, per_row_system, bkind, b,
+                                                  kind, C, grad, s);
+    } else if (an->n == 10) {
+        return launch_adjoint_wave<double, 10>(an, theta, B, coeffs, strings, L, per_row_system, bkind, b,
+                                               kind, C, grad, s);
+    }
+    return DVQ_EUNSUPPORTED;
+}
+
+}  // namespace dvq

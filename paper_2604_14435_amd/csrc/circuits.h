@@ -90,5 +90,12 @@ dvq_status make_terms_args(TermsArgs& g, const dvq_ansatz* an, const double* the
 dvq_status launch_terms(const TermsArgs& g, int precision, int exec, hipStream_t s);
 // Register-resident production kernels; DVQ_EUNSUPPORTED when the shape has none.
 dvq_status launch_terms_fast(const TermsArgs& g, int precision, hipStream_t s);
+dvq_status launch_terms_shared(const TermsArgs& g, int precision, hipStream_t s);
+// Register-resident adjoint (one wavefront per row); DVQ_EUNSUPPORTED when
+// the shape has none.
+dvq_status launch_adjoint_fast(const dvq_ansatz* an, const double* theta, int B, int precision,
+                               const dvq_c128* coeffs, const dvq_pauli* strings, int L,
+                               int per_row_system, int bkind, const double* b, int kind, double* C,
+                               double* grad, hipStream_t s);
 
 }  // namespace dvq

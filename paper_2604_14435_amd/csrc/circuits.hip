@@ -88,8 +88,9 @@ static dvq_status launch_generic(const TermsArgs& g, hipStream_t s) {
 }
 
 dvq_status launch_terms(const TermsArgs& g, int precision, int exec, hipStream_t s) {
-    if (exec == DVQ_EXEC_LITERAL) {
-        dvq_status st = launch_terms_fast(g, precision, s);
+    if (exec == DVQ_EXEC_LITERAL || exec == DVQ_EXEC_SHARED) {
+        dvq_status st = exec == DVQ_EXEC_LITERAL ? launch_terms_fast(g, precision, s)
+                                                 : launch_terms_shared(g, precision, s);
         if (st != DVQ_EUNSUPPORTED) return st;
     }
     return precision == DVQ_F32 ? launch_generic<float>(g, s) : launch_generic<double>(g, s);
@@ -150,6 +151,7 @@ extern "C" dvq_status dvq_vqls_terms(const dvq_ansatz* ansatz, const double* the
     dvq_status st = make_terms_args(g, ansatz, theta, B, precision, strings, L, b_kind, b,
                                     cost_kind, beta, other);
     if (st != DVQ_OK) return st;
-    DVQ_REQUIRE(exec == DVQ_EXEC_LITERAL || exec == DVQ_EXEC_GENERIC, "unknown exec %d", exec);
+    DVQ_REQUIRE(exec == DVQ_EXEC_LITERAL || exec == DVQ_EXEC_GENERIC || exec == DVQ_EXEC_SHARED,
+                "unknown exec %d", exec);
     return launch_terms(g, precision, exec, stream_of(stream));
 }

@@ -36,139 +36,19 @@
 // lane forms, for its k, a0 = psi0[k], a1 = (U psi1)[k], applies S^dagger,
 // the final H and accumulates |a0'|^2 - |a1'|^2.
 #include "circuits.h"
+#include "wave_state.h"
 
 namespace dvq {
 
-template <int NQ, bool HI>
-struct Lay {
-    static constexpr int RB = NQ - 5;
-    static constexpr int R = 1 << RB;
-    // register bit holding qubit q, or -1
-    static constexpr int reg(int q) {
-        return HI ? ((q >= 5 && q < NQ) ? q - 5 : -1) : ((q >= 0 && q < RB) ? q : -1);
-    }
-    // lane bit holding system qubit q, or -1
-    static constexpr int lanebit(int q) {
-        return HI ? ((q >= 0 && q < 5) ? q : -1) : ((q >= RB && q < NQ) ? q - RB : -1);
-    }
-    // global basis index of (lane, r)
-    __device__ static __forceinline__ int g(int lane, int r) {
-        return HI ? ((lane & 31) | (r << 5) | ((lane >> 5) << NQ))
-                  : (r | ((lane & 31) << RB) | ((lane >> 5) << NQ));
-    }
-};
-
-// LDS slot of basis index g: one pad amplitude every 32.
-__device__ __forceinline__ int pad_slot(int g) { return g + (g >> 5); }
-
-template <typename T, int NQ, bool HI, int Q, int PAR>
-__device__ __forceinline__ void ry_reg(T* re, T* im, int lane, T t, T s) {
-    using Ly = Lay<NQ, HI>;
-    constexpr int R = Ly::R;
-    constexpr int j = Ly::reg(Q);
-    static_assert(j >= 0, "qubit not in registers");
-    constexpr int lm = Q > 0 ? Ly::lanebit(Q - 1) : -1;
-    constexpr int lp = Q + 1 < NQ ? Ly::lanebit(Q + 1) : -1;
-    constexpr int rm = Q > 0 ? Ly::reg(Q - 1) : -1;
-    constexpr int rp = Q + 1 < NQ ? Ly::reg(Q + 1) : -1;
-    T tp = t, sp = s;
-    if constexpr (PAR) {
-        int rl = 0;
-        if constexpr (lm >= 0) rl ^= lane >> lm;
-        if constexpr (lp >= 0) rl ^= lane >> lp;
-        if (rl & 1) {
-            tp = -t;
-            sp = -s;
-        }
-    }
-    const T mtp = -tp, mtn = tp, spp = sp, spn = -sp;
-#pragma unroll
-    for (int r0 = 0; r0 < R; ++r0) {
-        if (r0 & (1 << j)) continue;
-        const int r1 = r0 | (1 << j);
-        bool neg = false;
-        if constexpr (PAR) {
-            if (rm >= 0) neg ^= (r0 >> rm) & 1;
-            if (rp >= 0) neg ^= (r0 >> rp) & 1;
-        }
-        const T mt = neg ? mtn : mtp;
-        const T ss = neg ? spn : spp;
-        re[r0] = fmat(mt, re[r1], re[r0]);
-        im[r0] = fmat(mt, im[r1], im[r0]);
-        re[r1] = fmat(ss, re[r0], re[r1]);
-        im[r1] = fmat(ss, im[r0], im[r1]);
-        re[r0] = fmat(mt, re[r1], re[r0]);
-        im[r0] = fmat(mt, im[r1], im[r0]);
-    }
-}
-
-// RY on every qubit q in [Q, QEND) that is a register qubit of the layout.
-template <typename T, int NQ, bool HI, int PAR, int Q, int QEND>
-__device__ __forceinline__ void ry_range(T* re, T* im, int lane, const T* trig, int kbase) {
-    if constexpr (Q < QEND) {
-        if constexpr (Lay<NQ, HI>::reg(Q) >= 0) {
-            const T t = trig[2 * (kbase + Q)], s = trig[2 * (kbase + Q) + 1];
-            ry_reg<T, NQ, HI, Q, PAR>(re, im, lane, t, s);
-        }
-        ry_range<T, NQ, HI, PAR, Q + 1, QEND>(re, im, lane, trig, kbase);
-    }
-}
-
-template <typename T, int NQ, bool FROM_HI>
-__device__ __forceinline__ void relayout(T* re, T* im, cplx<T>* S, int lane) {
-    constexpr int R = Lay<NQ, FROM_HI>::R;
-#pragma unroll
-    for (int r = 0; r < R; ++r) S[pad_slot(Lay<NQ, FROM_HI>::g(lane, r))] = {re[r], im[r]};
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const cplx<T> v = S[pad_slot(Lay<NQ, !FROM_HI>::g(lane, r))];
-        re[r] = v.re;
-        im[r] = v.im;
-    }
-    __syncthreads();
-}
-
-// Write the registers to LDS in natural order, applying S^p (the pending
-// CZ-ladder sign) on the way.
-template <typename T, int NQ, bool HI>
-__device__ __forceinline__ void store_state(const T* re, const T* im, cplx<T>* S, int lane, int p) {
-    constexpr int R = Lay<NQ, HI>::R;
-    constexpr int ladder = (1 << (NQ - 1)) - 1;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int g = Lay<NQ, HI>::g(lane, r);
-        const bool flip = p && (__popc((unsigned)(g & (g >> 1) & ladder)) & 1);
-        S[pad_slot(g)] = flip ? cplx<T>{-re[r], -im[r]} : cplx<T>{re[r], im[r]};
-    }
-    __syncthreads();
-}
-
+// The shared prefix of every circuit of one theta row: H on the ancilla and
+// V(theta) on the system register, left in LDS (natural order, padded) with
+// the pending CZ-ladder sign applied.  `trig` receives the rotation
+// parameters phi = theta/2 reduced to [-pi/2, pi/2]: tan(phi/2), sin(phi).
 template <typename T, int NQ>
-__global__ void __launch_bounds__(64) k_terms_fast(TermsArgs g) {
+__device__ __forceinline__ void simulate_prefix(const double* __restrict__ theta, int layers,
+                                                cplx<T>* S, T* trig, int lane) {
     constexpr int R = Lay<NQ, false>::R;
-    constexpr int N = 1 << NQ;
-    constexpr int NSLOT = 2 * N + (2 * N) / 32;
-    extern __shared__ __align__(16) unsigned char smem[];
-    cplx<T>* S = reinterpret_cast<cplx<T>*>(smem);
-    T* trig = reinterpret_cast<T*>(S + NSLOT);
-    const int lane = threadIdx.x;
-    const int layers = g.layers, P = NQ * layers;
-
-    const int64_t gid = (int64_t)blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
-    if (gid >= g.total) return;
-    const int64_t row = gid / g.per_row;
-    const Term t = decode_term(gid - row * g.per_row, g.L, NQ, g.kind);
-
-    // Rotation parameters of every gate: phi = theta/2 reduced to [-pi/2, pi/2].
-    for (int k = lane; k < P; k += 64) {
-        double ph = 0.5 * g.theta[row * P + k];
-        ph -= 3.14159265358979323846 * rint(ph * 0.31830988618379067154);
-        trig[2 * k] = (T)tan(0.5 * ph);
-        trig[2 * k + 1] = (T)sin(ph);
-    }
-    __syncthreads();
-
+    rotation_table<T>(theta, NQ * layers, trig, lane);
     // |0> with H on the ancilla: 1/sqrt(2) at g = 0 and g = 2^n (layout LO).
     T re[R], im[R];
 #pragma unroll
@@ -176,69 +56,198 @@ __global__ void __launch_bounds__(64) k_terms_fast(TermsArgs g) {
         re[r] = (r == 0 && (lane & 31) == 0) ? (T)0.70710678118654752440 : (T)0;
         im[r] = (T)0;
     }
-
-    int l = 0;
-    for (; l + 1 < layers; l += 2) {
-        // even layer (p = 0): LO qubits, swap, remaining HI qubits
-        ry_range<T, NQ, false, 0, 0, NQ>(re, im, lane, trig, l * NQ);
-        relayout<T, NQ, false>(re, im, S, lane);
-        ry_range<T, NQ, true, 0, Lay<NQ, false>::RB, NQ>(re, im, lane, trig, l * NQ);
-        // odd layer (p = 1): HI qubits, swap, remaining LO qubits
-        ry_range<T, NQ, true, 1, 0, NQ>(re, im, lane, trig, (l + 1) * NQ);
-        relayout<T, NQ, true>(re, im, S, lane);
-        ry_range<T, NQ, false, 1, 0, 5>(re, im, lane, trig, (l + 1) * NQ);
-    }
-    if (l < layers) {
-        ry_range<T, NQ, false, 0, 0, NQ>(re, im, lane, trig, l * NQ);
-        relayout<T, NQ, false>(re, im, S, lane);
-        ry_range<T, NQ, true, 0, Lay<NQ, false>::RB, NQ>(re, im, lane, trig, l * NQ);
-        store_state<T, NQ, true>(re, im, S, lane, 1);  // odd number of ladders
-    } else {
+    forward_layers<T, NQ>(re, im, S, trig, layers, lane);
+    if (layers & 1)
+        store_state<T, NQ, true>(re, im, S, lane, 1);
+    else
         store_state<T, NQ, false>(re, im, S, lane, 0);
-    }
+}
 
-    // Controlled U = A_l [X_j] A_m on the ancilla = 1 half as one signed permutation.
-    const dvq_pauli pl = g.strings[t.l], pm = g.strings[t.m];
-    const uint32_t xmid = pl.x ^ (t.type == kDelta ? (1u << t.j) : 0u);
-    const uint32_t X = xmid ^ pm.x, Z = pl.z ^ pm.z;
-    const int pw = (int)__popc(pl.x & pl.z) + (int)__popc(pm.x & pm.z) +
-                   2 * (int)((__popc(pl.z & pl.x) + __popc(pm.z & X)) & 1);
+// Controlled U = A_l [X_j] A_m on the ancilla = 1 half as one signed
+// permutation: (U psi)[k] = i^pw (-1)^{Z.k} psi[k ^ X].
+struct SignedPerm {
+    uint32_t X, Z;
+    int pw;
+};
+
+__device__ __forceinline__ SignedPerm suffix_perm(const dvq_pauli pl, const dvq_pauli pm, int type, int j) {
+    const uint32_t xmid = pl.x ^ (type == kDelta ? (1u << j) : 0u);
+    SignedPerm sp;
+    sp.X = xmid ^ pm.x;
+    sp.Z = pl.z ^ pm.z;
+    sp.pw = (int)__popc(pl.x & pl.z) + (int)__popc(pm.x & pm.z) +
+            2 * (int)((__popc(pl.z & pl.x) + __popc(pm.z & sp.X)) & 1);
+    return sp;
+}
+
+// <Z_anc> after applying U to the ancilla = 1 half, S^dagger (imag) and the
+// final H, summed over the lane's basis states and reduced over the wave.
+template <typename T, int NQ>
+__device__ __forceinline__ T measure_suffix(const cplx<T>* S, SignedPerm sp, int imag, int lane) {
+    constexpr int N = 1 << NQ;
     const T r2 = (T)0.70710678118654752440;
     T z = 0;
 #pragma unroll 4
     for (int i = 0; i < N / 64; ++i) {
         const int k = lane + 64 * i;
         const cplx<T> a0 = S[pad_slot(k)];
-        cplx<T> a1 = mul_ipow(S[pad_slot(N + (k ^ (int)X))],
-                              pw + 2 * (int)(__popc((unsigned)k & Z) & 1) + (t.part ? 3 : 0));
+        const cplx<T> a1 = mul_ipow(S[pad_slot(N + (k ^ (int)sp.X))],
+                                    sp.pw + 2 * (int)(__popc((unsigned)k & sp.Z) & 1) + (imag ? 3 : 0));
         const T b0r = (a0.re + a1.re) * r2, b0i = (a0.im + a1.im) * r2;
         const T b1r = (a0.re - a1.re) * r2, b1i = (a0.im - a1.im) * r2;
         z += (b0r * b0r + b0i * b0i) - (b1r * b1r + b1i * b1i);
     }
-    z = wave_sum(z);
+    return wave_sum(z);
+}
+
+// Both circuits (real, imaginary) of one term from one pass over the state:
+// the gathers and phases are shared, each circuit gets its own S^dagger,
+// H and <Z_anc>.
+template <typename T, int NQ>
+__device__ __forceinline__ void measure_suffix_pair(const cplx<T>* S, SignedPerm sp, int lane, T& zre,
+                                                    T& zim) {
+    constexpr int N = 1 << NQ;
+    const T r2 = (T)0.70710678118654752440;
+    T zr = 0, zi = 0;
+#pragma unroll 4
+    for (int i = 0; i < N / 64; ++i) {
+        const int k = lane + 64 * i;
+        const cplx<T> a0 = S[pad_slot(k)];
+        const cplx<T> a1 = mul_ipow(S[pad_slot(N + (k ^ (int)sp.X))],
+                                    sp.pw + 2 * (int)(__popc((unsigned)k & sp.Z) & 1));
+        // real-part circuit: H then <Z>
+        T b0r = (a0.re + a1.re) * r2, b0i = (a0.im + a1.im) * r2;
+        T b1r = (a0.re - a1.re) * r2, b1i = (a0.im - a1.im) * r2;
+        zr += (b0r * b0r + b0i * b0i) - (b1r * b1r + b1i * b1i);
+        // imaginary-part circuit: S^dagger (a1 -> -i a1), H, <Z>
+        const T c1r = a1.im, c1i = -a1.re;
+        b0r = (a0.re + c1r) * r2;
+        b0i = (a0.im + c1i) * r2;
+        b1r = (a0.re - c1r) * r2;
+        b1i = (a0.im - c1i) * r2;
+        zi += (b0r * b0r + b0i * b0i) - (b1r * b1r + b1i * b1i);
+    }
+    zre = wave_sum(zr);
+    zim = wave_sum(zi);
+}
+
+// Literal form: one wavefront simulates one circuit, every gate.
+template <typename T, int NQ>
+__global__ void __launch_bounds__(64) k_terms_fast(TermsArgs g) {
+    constexpr int N = 1 << NQ;
+    constexpr int NSLOT = 2 * N + (2 * N) / 32;
+    extern __shared__ __align__(16) unsigned char smem[];
+    cplx<T>* S = reinterpret_cast<cplx<T>*>(smem);
+    T* trig = reinterpret_cast<T*>(S + NSLOT);
+    const int lane = threadIdx.x;
+    const int P = NQ * g.layers;
+
+    const int64_t gid = (int64_t)blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
+    if (gid >= g.total) return;
+    const int64_t row = gid / g.per_row;
+    const Term t = decode_term(gid - row * g.per_row, g.L, NQ, g.kind);
+
+    simulate_prefix<T, NQ>(g.theta + row * P, g.layers, S, trig, lane);
+    const SignedPerm sp = suffix_perm(g.strings[t.l], g.strings[t.m], t.type, t.j);
+    const T z = measure_suffix<T, NQ>(S, sp, t.part, lane);
     if (lane == 0) store_term(g, row, t, (double)z);
+}
+
+// Prefix-shared form: one wavefront simulates the common prefix (H, V(theta))
+// once and then the distinct suffix of `chunk` consecutive circuits of the
+// same row (whole Re/Im pairs).  Same results as the literal form; the
+// ansatz work is paid once per chunk instead of once per circuit.
+template <typename T, int NQ>
+__global__ void __launch_bounds__(64) k_terms_shared(TermsArgs g, int64_t chunk, int64_t chunks_per_row) {
+    constexpr int N = 1 << NQ;
+    constexpr int NSLOT = 2 * N + (2 * N) / 32;
+    extern __shared__ __align__(16) unsigned char smem[];
+    cplx<T>* S = reinterpret_cast<cplx<T>*>(smem);
+    T* trig = reinterpret_cast<T*>(S + NSLOT);
+    const int lane = threadIdx.x;
+    const int P = NQ * g.layers;
+
+    const int64_t wg = (int64_t)blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
+    const int64_t row = wg / chunks_per_row;
+    if (row >= g.B) return;
+    const int64_t c0 = (wg - row * chunks_per_row) * chunk;
+    const int64_t c1 = c0 + chunk < g.per_row ? c0 + chunk : g.per_row;
+
+    simulate_prefix<T, NQ>(g.theta + row * P, g.layers, S, trig, lane);
+    for (int64_t c = c0; c < c1; c += 2) {
+        const Term t = decode_term(c, g.L, NQ, g.kind);
+        const SignedPerm sp = suffix_perm(g.strings[t.l], g.strings[t.m], t.type, t.j);
+        T zr, zi;
+        measure_suffix_pair<T, NQ>(S, sp, lane, zr, zi);
+        if (lane == 0) {
+            store_term(g, row, t, (double)zr);
+            Term ti = t;
+            ti.part = 1;
+            store_term(g, row, ti, (double)zi);
+        }
+    }
+}
+
+template <typename T, int NQ>
+static size_t fast_lds_bytes(int layers) {
+    constexpr int N = 1 << NQ;
+    return (size_t)(2 * N + (2 * N) / 32) * sizeof(cplx<T>) + (size_t)2 * NQ * layers * sizeof(T);
 }
 
 template <typename T, int NQ>
 static dvq_status launch_fast(const TermsArgs& g, hipStream_t s) {
-    constexpr int N = 1 << NQ;
-    const size_t lds = (size_t)(2 * N + (2 * N) / 32) * sizeof(cplx<T>) +
-                       (size_t)2 * NQ * g.layers * sizeof(T);
+    const size_t lds = fast_lds_bytes<T, NQ>(g.layers);
     DVQ_TRY_HIP(allow_lds((const void*)k_terms_fast<T, NQ>, lds));
     hipLaunchKernelGGL((k_terms_fast<T, NQ>), grid_for(g.total), dim3(64), lds, s, g);
     DVQ_CHECK_LAUNCH("k_terms_fast");
     return DVQ_OK;
 }
 
+// Circuits per wavefront in the prefix-shared form: enough wavefronts to
+// cover the chip several times over, chunks of whole Re/Im pairs.
+static int64_t shared_chunk(int64_t per_row, int B) {
+    const int64_t target_waves = 8192;
+    int64_t per_row_waves = (target_waves + B - 1) / B;
+    int64_t chunk = (per_row + per_row_waves - 1) / per_row_waves;
+    if (chunk < 64) chunk = 64;
+    chunk = (chunk + 1) & ~int64_t(1);
+    return chunk;
+}
+
+template <typename T, int NQ>
+static dvq_status launch_shared(const TermsArgs& g, hipStream_t s) {
+    const size_t lds = fast_lds_bytes<T, NQ>(g.layers);
+    DVQ_TRY_HIP(allow_lds((const void*)k_terms_shared<T, NQ>, lds));
+    const int64_t chunk = shared_chunk(g.per_row, g.B);
+    const int64_t cpr = (g.per_row + chunk - 1) / chunk;
+    hipLaunchKernelGGL((k_terms_shared<T, NQ>), grid_for(cpr * g.B), dim3(64), lds, s, g, chunk, cpr);
+    DVQ_CHECK_LAUNCH("k_terms_shared");
+    return DVQ_OK;
+}
+
+static bool fast_shape(const TermsArgs& g) {
+    return g.kind == DVQ_COST_LOCAL && g.bkind == DVQ_B_PLUS && g.ent == DVQ_ENT_CZ_LADDER &&
+           g.n * g.layers <= 1024;
+}
+
 dvq_status launch_terms_fast(const TermsArgs& g, int precision, hipStream_t s) {
-    if (g.kind != DVQ_COST_LOCAL || g.bkind != DVQ_B_PLUS || g.ent != DVQ_ENT_CZ_LADDER)
-        return DVQ_EUNSUPPORTED;
-    if (g.n * g.layers > 1024) return DVQ_EUNSUPPORTED;
+    if (!fast_shape(g)) return DVQ_EUNSUPPORTED;
     if (precision == DVQ_F32) {
         if (g.n == 10) return launch_fast<float, 10>(g, s);
         if (g.n == 11) return launch_fast<float, 11>(g, s);
     } else {
         if (g.n == 10) return launch_fast<double, 10>(g, s);
+    }
+    return DVQ_EUNSUPPORTED;
+}
+
+dvq_status launch_terms_shared(const TermsArgs& g, int precision, hipStream_t s) {
+    if (!fast_shape(g)) return DVQ_EUNSUPPORTED;
+    if (precision == DVQ_F32) {
+        if (g.n == 10) return launch_shared<float, 10>(g, s);
+        if (g.n == 11) return launch_shared<float, 11>(g, s);
+    } else {
+        if (g.n == 10) return launch_shared<double, 10>(g, s);
     }
     return DVQ_EUNSUPPORTED;
 }

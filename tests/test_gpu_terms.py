@@ -161,3 +161,29 @@ def test_wavefront_kernel_shapes(n, layers, precision):
             assert abs(beta[r, l, m] - qc.beta_term(th[r], n, layers, "cz", sl, sm)) < tol
             j = int(rng.integers(0, n))
             assert abs(delta[r, j, l, m] - qc.delta_term(th[r], n, layers, "cz", sl, sm, j)) < tol
+
+
+@pytest.mark.parametrize("n,layers,precision", [(10, 4, "f32"), (10, 3, "f64"), (11, 2, "f32")])
+def test_prefix_shared_mode(n, layers, precision):
+    """Prefix-shared execution (ansatz once per wavefront, each circuit's own
+    gates on a copy): B = 3 rows, ragged L = 9; sampled terms against the
+    oracle's circuits and every term against the literal kernel."""
+    rng = np.random.default_rng(7 * n + layers)
+    N = 1 << n
+    strings = rng.integers(0, N, size=(9, 2)).astype(np.int32)
+    strings[2] = (0, 0)
+    th = rng.uniform(0, 2 * math.pi, size=(3, n * layers))
+    an = api.AnsatzSpec(n, layers, "cz")
+    bs, ds = api.vqls_terms(an, _gpu(th), _gpu(strings), "local", precision, exec_="shared")
+    bl, dl = api.vqls_terms(an, _gpu(th), _gpu(strings), "local", precision, exec_="literal")
+    tol = TOL[precision]
+    assert torch.max(torch.abs(bs - bl)).item() < 2 * tol
+    assert torch.max(torch.abs(ds - dl)).item() < 2 * tol
+    bs, ds = bs.cpu().numpy(), ds.cpu().numpy()
+    for r in range(3):
+        for _ in range(3):
+            l, m = (int(v) for v in rng.integers(0, 9, 2))
+            sl, sm = (int(strings[l, 0]), int(strings[l, 1])), (int(strings[m, 0]), int(strings[m, 1]))
+            assert abs(bs[r, l, m] - qc.beta_term(th[r], n, layers, "cz", sl, sm)) < tol
+            j = int(rng.integers(0, n))
+            assert abs(ds[r, j, l, m] - qc.delta_term(th[r], n, layers, "cz", sl, sm, j)) < tol
