@@ -79,6 +79,118 @@ def cpu_baseline(seconds: float):
                       f"gate by gate in NumPy float64, {el:.1f} s on one core"}
 
 
+def warm_start_experiment(api, dev, n, layers, eta, budget, epochs, family_iters, seed_rand=0):
+    """Learned warm start on the Toeplitz family (a, b) ~ U([0.8,1.2] x [-0.49,-0.1]),
+    4096 systems, top-64 terms, seeded 3584/512 split.  Training angles come
+    from the solver itself (adjoint gradient descent, every system started
+    from the solution of the centre system (1.0, -0.3)).  Returns the
+    held-out statistics, the trained network and the timings."""
+    import numpy as np
+    import torch
+
+    from paper_2604_14435_amd.warmstart import (MLPConfig, WarmStartMLP, decompose_family,
+                                                iterations_to, solve)
+    from workloads import family_split, theta_uniform, toeplitz, toeplitz_family
+
+    an = api.AnsatzSpec(n, layers, "cz")
+    t0 = time.perf_counter()
+    ab = toeplitz_family(4096, seed=0)
+    coeffs, strings, _ = decompose_family([toeplitz(n, a, b) for a, b in ab], 64, dev)
+    torch.cuda.synchronize()
+    t_dec = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    c0, s0, _ = decompose_family([toeplitz(n, 1.0, -0.3)], 64, dev)
+    th_r = torch.from_numpy(theta_uniform(an.P, seed=seed_rand)).to(dev).unsqueeze(0)
+    th0, _ = solve(an, c0, s0, th_r, family_iters, eta, record=False)
+    theta_star, hist = solve(an, coeffs, strings, th0.repeat(4096, 1), family_iters, eta)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    tr, te = family_split(4096, 3584, seed=1)
+    t0 = time.perf_counter()
+    net = WarmStartMLP(2, an.P, MLPConfig(hidden=256, epochs=epochs, batch=256, lr=1e-3), dev)
+    losses = net.fit(ab[tr], theta_star[tr])
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    pred = net.predict(ab[te])
+    rand = torch.from_numpy(np.stack([theta_uniform(an.P, seed=1000 + int(i)) for i in te])).to(dev)
+    ct, st = coeffs[te].contiguous(), strings[te].contiguous()
+    _, hr = solve(an, ct, st, rand, budget, eta)
+    _, hw = solve(an, ct, st, pred, budget, eta)
+    thr = torch.clamp(hr[-1] + 1e-4, min=1e-4)
+    itr = iterations_to(hr, thr).cpu().numpy()
+    itw = iterations_to(hw, thr).cpu().numpy()
+    reached_w = itw >= 0
+    stats = {
+        "systems": {"train": int(len(tr)), "held_out": int(len(te))},
+        "budget_iters": budget,
+        "threshold": "per system: max(1e-4, random-init cost after the budget + 1e-4)",
+        "median_cost_start": {"random": float(hr[0].median()), "mlp": float(hw[0].median())},
+        "median_cost_after_budget": {"random": float(hr[-1].median()), "mlp": float(hw[-1].median())},
+        "median_iters_to_threshold": {"random": float(np.median(itr)),
+                                      "mlp_reached": float(np.median(itw[reached_w])) if reached_w.any() else None},
+        "fraction_reaching_threshold": {"random": float(np.mean(itr >= 0)), "mlp": float(np.mean(reached_w))},
+        "mlp_loss": {"first_epoch": float(losses[0]), "last_epoch": float(losses[-1])},
+        "seconds": {"decompose_family": round(t_dec, 3), "generate_training_angles": round(t_data, 3),
+                    "train_mlp": round(t_train, 3)},
+    }
+    return stats, net
+
+
+def time_to_solution(api, dev, an, coeffs, strings, theta_rand, fast_s, plain_s, budget):
+    """Seconds to solution on the benchmark system: plain form = complex128
+    circuits + shift-rule gradient from random initialisation; fast form =
+    complex64 circuits + adjoint gradient from the learned warm start (random
+    initialisation as the fallback).  The iteration counts come from the
+    exact-gradient trajectories (the shift rule and the float64 adjoint give
+    the same gradient to ~1e-12, checked on the first iterations below); the
+    seconds are those counts times the measured per-iteration times."""
+    import numpy as np
+    import torch
+
+    from paper_2604_14435_amd.warmstart import choose_start, iterations_to, solve
+
+    stats, net = warm_start_experiment(api, dev, an.n, an.layers, ETA, budget, epochs=300,
+                                       family_iters=1500)
+    th_r = theta_rand.unsqueeze(0)
+    t0 = time.perf_counter()
+    pred = net.predict(np.array([[DIAG, OFFDIAG]]))
+    start, used = choose_start(an, coeffs.unsqueeze(0), strings.unsqueeze(0), pred, th_r)
+    torch.cuda.synchronize()
+    t_predict = time.perf_counter() - t0
+    _, h_plain = solve(an, coeffs, strings, th_r, budget, ETA, precision="f64", per_row_system=False)
+    _, h_fast = solve(an, coeffs, strings, start, budget, ETA, precision="f32", per_row_system=False)
+    thr = torch.clamp(h_plain[-1] + 1e-4, min=1e-4)
+    it_plain = int(iterations_to(h_plain, thr)[0])
+    it_fast = int(iterations_to(h_fast, thr)[0])
+    fallback = it_fast < 0
+    if fallback:
+        _, h_fast = solve(an, coeffs, strings, th_r, budget, ETA, precision="f32", per_row_system=False)
+        it_fast = int(iterations_to(h_fast, thr)[0])
+    # the shift-rule trajectory itself, first iterations, against the f64 adjoint one
+    th_ps = theta_rand.clone()
+    ws = api.ShiftWorkspace(an, coeffs.shape[0], "local", dev)
+    th_ad, _ = solve(an, coeffs, strings, th_r, 3, ETA, precision="f64", per_row_system=False, record=False)
+    for _ in range(3):
+        _, g = api.vqls_grad_shift(an, th_ps, coeffs, strings, "local", "f64", workspace=ws)
+        api.gd_step(th_ps, g, ETA)
+    traj_dev = float(torch.max(torch.abs(th_ps - th_ad[0])).item())
+    tts = {
+        "system": "toeplitz_n10_L64 (a=1.0, b=-0.45), CZ ladder, local cost, eta=%g" % ETA,
+        "threshold_cost": float(thr[0]),
+        "plain_fp64_shift_random_init": {"iterations": it_plain,
+                                         "seconds": round(it_plain * plain_s, 4) if it_plain >= 0 else None},
+        "fp32_adjoint_warm_start": {"iterations": it_fast, "fallback_to_random_init": bool(fallback),
+                                    "prediction_used": bool(used[0]),
+                                    "start_cost": float(h_fast[0, 0]),
+                                    "seconds": round(it_fast * fast_s + t_predict, 4) if it_fast >= 0 else None},
+        "trajectory_check_shift_vs_adjoint_3_iters": traj_dev,
+        "method": "iterations on the exact-gradient trajectories x measured seconds per iteration",
+    }
+    if it_plain >= 0 and it_fast >= 0:
+        tts["speedup"] = round((it_plain * plain_s) / (it_fast * fast_s + t_predict), 1)
+    return stats, tts
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +202,9 @@ def main() -> int:
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (calibrates HBM counters)")
     ap.add_argument("--no-fwht", action="store_true")
+    ap.add_argument("--no-warmstart", action="store_true")
+    ap.add_argument("--tts-budget", type=int, default=2000,
+                    help="iteration budget of the time-to-solution comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -262,6 +377,9 @@ def main() -> int:
                           "note": "same circuits and results; the ansatz prefix simulated once per wavefront"},
         "roofline_fwht": fwht,
     }
+    if not args.no_warmstart:
+        out["warm_start"], out["time_to_solution"] = time_to_solution(
+            api, dev, an, coeffs, strings, theta0, fast_s, plain_s, args.tts_budget)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out))

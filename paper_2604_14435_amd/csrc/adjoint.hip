@@ -140,11 +140,13 @@ k_adjoint(const double* __restrict__ theta, int n, int layers, int ent,
 
     // reverse sweep
     for (int l = layers - 1; l >= 0; --l) {
-        for (int q = n - 2; q >= 0; --q) {
-            if (ent == DVQ_ENT_CZ_LADDER) {
-                lds_cz<T>(psi, n, q, q + 1, -1);
-                lds_cz<T>(lam, n, q, q + 1, -1);
-            } else {
+        if (ent == DVQ_ENT_CZ_LADDER) {
+            if (n > 1) {
+                lds_cz_ladder<T>(psi, n, n, -1);
+                lds_cz_ladder<T>(lam, n, n, -1);
+            }
+        } else {
+            for (int q = n - 2; q >= 0; --q) {
                 lds_cx<T>(psi, n, q, q + 1, -1);
                 lds_cx<T>(lam, n, q, q + 1, -1);
             }

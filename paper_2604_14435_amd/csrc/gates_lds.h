@@ -51,6 +51,20 @@ __device__ void lds_cz(cplx<T>* a, int nb, int q1, int q2, int ctrl) {
     __syncthreads();
 }
 
+// The whole CZ ladder CZ(0,1) CZ(1,2) ... CZ(n-2,n-1) as one diagonal pass:
+// the sign of basis state i is (-1)^{sum_q i_q i_{q+1}} (optionally only
+// where bit ctrl is 1).
+template <typename T>
+__device__ void lds_cz_ladder(cplx<T>* a, int nb, int n, int ctrl) {
+    const int na = 1 << nb;
+    const uint32_t ladder = (1u << (n - 1)) - 1u;
+    for (int i = threadIdx.x; i < na; i += blockDim.x) {
+        if (ctrl >= 0 && !((i >> ctrl) & 1)) continue;
+        if (parity((uint32_t)i & ((uint32_t)i >> 1) & ladder)) a[i] = {-a[i].re, -a[i].im};
+    }
+    __syncthreads();
+}
+
 // CNOT(control c, target t), optionally controlled (then a Toffoli).
 template <typename T>
 __device__ void lds_cx(cplx<T>* a, int nb, int c, int t, int ctrl) {
@@ -124,11 +138,10 @@ __device__ void lds_ansatz(cplx<T>* a, int nb, int n, int layers, int ent, const
             const int k = l * n + q;
             lds_ry<T>(a, nb, q, trig[2 * k], trig[2 * k + 1], ctrl);
         }
-        for (int q = 0; q + 1 < n; ++q) {
-            if (ent == DVQ_ENT_CZ_LADDER)
-                lds_cz<T>(a, nb, q, q + 1, ctrl);
-            else
-                lds_cx<T>(a, nb, q, q + 1, ctrl);
+        if (ent == DVQ_ENT_CZ_LADDER) {
+            if (n > 1) lds_cz_ladder<T>(a, nb, n, ctrl);
+        } else {
+            for (int q = 0; q + 1 < n; ++q) lds_cx<T>(a, nb, q, q + 1, ctrl);
         }
     }
 }

@@ -1,0 +1,52 @@
+"""Summarise rocprofv3 CSV output for the profiles/ notes.
+
+    python -m paper_2604_14435_amd.profile_summary stats  <dir>/<name>_kernel_stats.csv
+    python -m paper_2604_14435_amd.profile_summary counter <dir>/<name>_counter_collection.csv [filter]
+
+`stats` prints calls and average / min / max duration per kernel.
+`counter` prints, per kernel name (optionally only names containing
+`filter`), the number of dispatches and the average counter value per
+dispatch (FETCH_SIZE / WRITE_SIZE are reported by the hardware in KiB).
+"""
+from __future__ import annotations
+
+import csv
+import sys
+from collections import defaultdict
+
+
+def stats(path: str) -> None:
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    print(f"{'kernel':72s} {'calls':>6s} {'avg_us':>11s} {'min_us':>11s} {'max_us':>11s} {'pct':>7s}")
+    for r in rows:
+        print(f"{r['Name'][:72]:72s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:11.3f} "
+              f"{float(r['MinNs']) / 1e3:11.3f} {float(r['MaxNs']) / 1e3:11.3f} {float(r['Percentage']):7.2f}")
+
+
+def counter(path: str, flt: str | None = None) -> None:
+    rows = list(csv.DictReader(open(path)))
+    name_key = "Kernel_Name" if "Kernel_Name" in rows[0] else "Name"
+    acc = defaultdict(lambda: defaultdict(list))
+    for r in rows:
+        name = r[name_key]
+        if flt and flt not in name:
+            continue
+        acc[name][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    for name, ctrs in acc.items():
+        for c, vals in ctrs.items():
+            print(f"{name[:72]:72s} {c:12s} dispatches={len(vals):5d} avg_per_dispatch={sum(vals) / len(vals):14.1f}")
+
+
+def main() -> None:
+    if len(sys.argv) < 3:
+        print(__doc__)
+        sys.exit(2)
+    if sys.argv[1] == "stats":
+        stats(sys.argv[2])
+    else:
+        counter(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else None)
+
+
+if __name__ == "__main__":
+    main()
