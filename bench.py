@@ -159,15 +159,27 @@ def time_to_solution(api, dev, an, coeffs, strings, theta_rand, fast_s, plain_s,
     start, used = choose_start(an, coeffs.unsqueeze(0), strings.unsqueeze(0), pred, th_r)
     torch.cuda.synchronize()
     t_predict = time.perf_counter() - t0
-    _, h_plain = solve(an, coeffs, strings, th_r, budget, ETA, precision="f64", per_row_system=False)
-    _, h_fast = solve(an, coeffs, strings, start, budget, ETA, precision="f32", per_row_system=False)
+    th_pf, h_plain = solve(an, coeffs, strings, th_r, budget, ETA, precision="f64", per_row_system=False)
+    th_ff, h_fast = solve(an, coeffs, strings, start, budget, ETA, precision="f32", per_row_system=False)
     thr = torch.clamp(h_plain[-1] + 1e-4, min=1e-4)
     it_plain = int(iterations_to(h_plain, thr)[0])
     it_fast = int(iterations_to(h_fast, thr)[0])
     fallback = it_fast < 0
     if fallback:
-        _, h_fast = solve(an, coeffs, strings, th_r, budget, ETA, precision="f32", per_row_system=False)
+        th_ff, h_fast = solve(an, coeffs, strings, th_r, budget, ETA, precision="f32", per_row_system=False)
         it_fast = int(iterations_to(h_fast, thr)[0])
+    # fidelity of the final states against the classical solutions of the
+    # pruned system (A_tilde from the kept terms) and of the full system
+    from workloads import plus_state, toeplitz
+    At = api.pauli_sum_dense(coeffs, strings, an.n).cpu().numpy()
+    bvec = plus_state(an.n)
+    fids = {}
+    for name, M in (("vs_pruned_solution", At), ("vs_full_solution", toeplitz(an.n, DIAG, OFFDIAG))):
+        xs = np.linalg.solve(M, bvec.astype(M.dtype))
+        xs = xs / np.linalg.norm(xs)
+        tgt = torch.from_numpy(xs.astype(np.complex128)).to(dev)
+        fids[name] = {"plain_final": float(api.fidelity(an, th_pf, tgt)[0]),
+                      "fast_final": float(api.fidelity(an, th_ff, tgt)[0])}
     # the shift-rule trajectory itself, first iterations, against the f64 adjoint one
     th_ps = theta_rand.clone()
     ws = api.ShiftWorkspace(an, coeffs.shape[0], "local", dev)
@@ -186,6 +198,8 @@ def time_to_solution(api, dev, an, coeffs, strings, theta_rand, fast_s, plain_s,
                                     "start_cost": float(h_fast[0, 0]),
                                     "seconds": round(it_fast * fast_s + t_predict, 4) if it_fast >= 0 else None},
         "trajectory_check_shift_vs_adjoint_3_iters": traj_dev,
+        "final_cost": {"plain": float(h_plain[-1, 0]), "fast": float(h_fast[-1, 0])},
+        "fidelity": fids,
         "method": "iterations on the exact-gradient trajectories x measured seconds per iteration",
     }
     if it_plain >= 0 and it_fast >= 0:

@@ -135,6 +135,14 @@ dvq_status dvq_pauli_decompose(const double* A, int32_t n, double tau, int64_t t
                                int64_t* L_out_host, double* frob_err_host,
                                void* workspace, size_t workspace_bytes, dvq_stream stream);
 
+/*
+ * Dense operator of a term list: out[r][c] = sum_l c_l P_l[r][c] (Eq. (3)),
+ * complex128 [2^n][2^n] row-major (e.g. the pruned matrix A_tilde).
+ *   coeffs [L], strings [L] as written by dvq_pauli_decompose; n 1..14.
+ */
+dvq_status dvq_pauli_sum_dense(const dvq_c128* coeffs, const dvq_pauli* strings, int32_t L,
+                               int32_t n, dvq_c128* out, dvq_stream stream);
+
 /* ----------------------------------------------- Hadamard-test circuits */
 
 /* Number of circuits one cost evaluation simulates for one theta row:

@@ -91,6 +91,16 @@ def pauli_decompose(A: torch.Tensor, tau: float | None = None, top_L: int | None
     return coeffs[:k].clone(), strings[:k].clone(), ferr.value
 
 
+def pauli_sum_dense(coeffs: torch.Tensor, strings: torch.Tensor, n: int) -> torch.Tensor:
+    """sum_l c_l P_l as a dense complex128 [2^n, 2^n] matrix."""
+    coeffs = _cuda(coeffs, torch.complex128, "coeffs")
+    strings = _cuda(strings, torch.int32, "strings")
+    N = 1 << n
+    out = torch.empty((N, N), dtype=torch.complex128, device=coeffs.device)
+    L.call("dvq_pauli_sum_dense", _p(coeffs), _p(strings), coeffs.shape[0], n, _p(out), _stream(coeffs))
+    return out
+
+
 # -------------------------------------------------------------- circuits / cost
 
 def circuit_count(n: int, L_: int, kind: str) -> int:

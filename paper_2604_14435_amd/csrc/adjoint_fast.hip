@@ -127,24 +127,35 @@ __device__ __forceinline__ void store_half0(const T* re, const T* im, cplx<T>* S
     __syncthreads();
 }
 
-// out[k] = sum_l w_l (P_l in)[k] over natural-order regions, w_l = c_l or conj(c_l).
+// out[k] = sum_l w_l (P_l in)[k] over natural-order regions, w_l = c_l or
+// conj(c_l).  (P in)[k] = i^{|x&z|} (-1)^{|z&x|} (-1)^{|z&k|} in[k^x]; with
+// k = lane + 64 i the last sign splits into a per-lane and a per-i part, so
+// the coefficient carries everything but the per-i sign, and each string
+// issues 2^NQ/64 independent gathers.
 template <typename T, int NQ>
 __device__ __forceinline__ void wave_pauli_sum(cplx<T>* out, const cplx<T>* in, const dvq_pauli* sp,
                                                const dvq_c128* cp, int L, bool conj_c, int lane) {
-    constexpr int N = 1 << NQ;
-    for (int i = 0; i < N / 64; ++i) {
-        const int k = lane + 64 * i;
-        T ar = 0, ai = 0;
-        for (int l = 0; l < L; ++l) {
-            const uint32_t x = sp[l].x, z = sp[l].z;
-            const int kk = k ^ (int)x;
-            const cplx<T> v = mul_ipow(in[pad_slot(kk)], (int)__popc(x & z) + 2 * parity(z & (uint32_t)kk));
-            const T cr = (T)cp[l].re, ci = conj_c ? -(T)cp[l].im : (T)cp[l].im;
-            ar += cr * v.re - ci * v.im;
-            ai += cr * v.im + ci * v.re;
+    constexpr int KPL = (1 << NQ) / 64;
+    T ar[KPL], ai[KPL];
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) ar[i] = ai[i] = (T)0;
+    for (int l = 0; l < L; ++l) {
+        const uint32_t x = sp[l].x, z = sp[l].z;
+        cplx<T> c = {(T)cp[l].re, conj_c ? -(T)cp[l].im : (T)cp[l].im};
+        c = mul_ipow(c, (int)__popc(x & z) + 2 * parity(z & x) + 2 * parity(z & (uint32_t)lane));
+        const int xl = (int)(x & 63u), xh = (int)(x >> 6);
+#pragma unroll
+        for (int i = 0; i < KPL; ++i) {
+            const int kk = ((lane ^ xl) | ((i ^ xh) << 6));
+            const cplx<T> v = in[pad_slot(kk)];
+            const bool neg = parity(z & (uint32_t)(64 * i));
+            const T cr = neg ? -c.re : c.re, ci = neg ? -c.im : c.im;
+            ar[i] += cr * v.re - ci * v.im;
+            ai[i] += cr * v.im + ci * v.re;
         }
-        out[pad_slot(k)] = {ar, ai};
     }
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) out[pad_slot(lane + 64 * i)] = {ar[i], ai[i]};
     __syncthreads();
 }
 

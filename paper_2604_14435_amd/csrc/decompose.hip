@@ -277,6 +277,32 @@ k_sum_partials(const double* __restrict__ partials, int count, double* __restric
     if (threadIdx.x == 0) *out = s;
 }
 
+// A_tilde[r][c] = sum_l c_l P_l[r][c], P[r][c] = i^{|x&z|} (-1)^{|z&c|} [r == c^x]
+// (Eq. (3) with the kept terms).  One thread per matrix entry.
+__global__ void __launch_bounds__(256)
+k_pauli_sum_dense(const dvq_c128* __restrict__ coeffs, const dvq_pauli* __restrict__ strings, int L,
+                  int n, dvq_c128* __restrict__ out) {
+    const int64_t N = int64_t(1) << n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N * N;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t r = (uint32_t)(e >> n), c = (uint32_t)(e & (N - 1));
+        double ar = 0.0, ai = 0.0;
+        for (int l = 0; l < L; ++l) {
+            const dvq_pauli p = strings[l];
+            if ((c ^ p.x) != r) continue;
+            const int ph = (int)__popc(p.x & p.z) + 2 * parity(p.z & c);
+            const dvq_c128 w = coeffs[l];
+            switch (ph & 3) {  // w * i^ph
+                case 0: ar += w.re; ai += w.im; break;
+                case 1: ar -= w.im; ai += w.re; break;
+                case 2: ar -= w.re; ai -= w.im; break;
+                default: ar += w.im; ai -= w.re; break;
+            }
+        }
+        out[e] = {ar, ai};
+    }
+}
+
 struct DecWs {
     double* T;
     double* values;
@@ -326,6 +352,19 @@ static int stream_blocks(int64_t total) {
 using namespace dvq;
 
 extern "C" {
+
+dvq_status dvq_pauli_sum_dense(const dvq_c128* coeffs, const dvq_pauli* strings, int32_t L, int32_t n,
+                               dvq_c128* out, dvq_stream stream) {
+    DVQ_REQUIRE(n >= 1 && n <= 14, "n=%d outside 1..14", n);
+    DVQ_REQUIRE(L >= 0, "L < 0");
+    DVQ_REQUIRE(out && (L == 0 || (coeffs && strings)), "null device pointer");
+    const int64_t total = int64_t(1) << (2 * n);
+    const int64_t blocks = (total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536;
+    hipLaunchKernelGGL(k_pauli_sum_dense, dim3((unsigned)blocks), dim3(256), 0, stream_of(stream), coeffs,
+                       strings, L, n, out);
+    DVQ_CHECK_LAUNCH("k_pauli_sum_dense");
+    return DVQ_OK;
+}
 
 size_t dvq_decompose_workspace_bytes(int32_t n) {
     if (n < 1 || n > 12) return 0;

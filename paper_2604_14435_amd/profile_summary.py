@@ -5,8 +5,10 @@
 
 `stats` prints calls and average / min / max duration per kernel.
 `counter` prints, per kernel name (optionally only names containing
-`filter`), the number of dispatches and the average counter value per
-dispatch (FETCH_SIZE / WRITE_SIZE are reported by the hardware in KiB).
+`filter`) and launch grid size, the number of dispatches and the average
+counter value per dispatch (FETCH_SIZE / WRITE_SIZE are reported by the
+hardware in KiB). Grouping by grid keeps calls of one kernel on different
+problem sizes apart.
 """
 from __future__ import annotations
 
@@ -32,10 +34,12 @@ def counter(path: str, flt: str | None = None) -> None:
         name = r[name_key]
         if flt and flt not in name:
             continue
-        acc[name][r["Counter_Name"]].append(float(r["Counter_Value"]))
-    for name, ctrs in acc.items():
+        grid = int(r.get("Grid_Size", 0) or 0)
+        acc[(name, grid)][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    for (name, grid), ctrs in acc.items():
         for c, vals in ctrs.items():
-            print(f"{name[:72]:72s} {c:12s} dispatches={len(vals):5d} avg_per_dispatch={sum(vals) / len(vals):14.1f}")
+            print(f"{name[:64]:64s} grid={grid:<10d} {c:11s} dispatches={len(vals):4d} "
+                  f"avg_per_dispatch={sum(vals) / len(vals):13.1f}")
 
 
 def main() -> None:

@@ -135,3 +135,19 @@ def test_n1_smallest():
     A = np.array([[2.0, -0.5], [0.25, 1.0]])
     got = api.pauli_decompose_dense(_gpu(A)).cpu().numpy()
     assert np.max(np.abs(got - op.decompose_bruteforce(A))) < 1e-15
+
+
+@pytest.mark.parametrize("n,L_", [(3, 8), (6, 20), (10, 64)])
+def test_pauli_sum_dense_reconstructs(n, L_):
+    """sum_l c_l P_l against the oracle's Kronecker-product reconstruction;
+    with every term kept (n = 3) it returns A itself."""
+    A = random_symmetric(n, seed=n) if n < 10 else toeplitz(n, 1.0, -0.45)
+    C = op.decompose_fwht(A)
+    keep = op.select_top(C, L_ if n > 3 else 4 ** n)
+    c, xs, zs = op.kept_terms(C, keep)
+    strings = np.stack([xs, zs], 1).astype(np.int32)
+    got = api.pauli_sum_dense(_gpu(c), _gpu(strings), n).cpu().numpy()
+    want = op.reconstruct(c, xs, zs, n)
+    assert np.max(np.abs(got - want)) < 1e-13
+    if n == 3:
+        assert np.max(np.abs(got - A)) < 1e-13
