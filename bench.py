@@ -9,7 +9,8 @@ Workload: n = 10 tridiagonal Toeplitz system A = tridiag(-0.45, 1, -0.45)
 One timed step = one VQLS iteration of the fast form:
   every circuit of the cost evaluation simulated with complex64 state
   vectors (float64 accumulation of the terms into the cost), the adjoint
-  gradient (complex64 states) and the gradient-descent update.
+  gradient (complex64 states, on a second stream beside the circuits: both
+  read the angles only) and the gradient-descent update after both.
 The plain form (complex128 states, gradient by the parameter-shift rule:
 (2P + 1) x 90,112 circuits per iteration) is timed beside it.
 
@@ -32,6 +33,44 @@ METRIC = "circuits/s + s/VQLS-iter @ n=10 L=64: FP32+adjoint+warm-start vs plain
 FP32_ALU_PEAK = 78.6   # TFLOP/s: 256 CU x 4 SIMD x 16 lanes x FMA (2 flop) x 2.4 GHz, non-packed
 FP64_ALU_PEAK = 78.6   # TFLOP/s: MI355X float64 vector peak
 N_QUBITS, LAYERS, TAU, DIAG, OFFDIAG, ETA = 10, 4, 0.01, 1.0, -0.45, 2.0
+CSRC = os.path.join(ROOT, "paper_2604_14435_amd", "csrc")
+
+# HBM bytes per dispatch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this
+# bench (profiles/bench_toeplitz_n10_L64_hbm_counters.txt), scaled by what the
+# same counters read for a 256 MiB device copy (FETCH x 2.000, WRITE x 1.000).
+# Valid only for the kernel sources they were taken on: `sources_sha256` is
+# checked at run time and the figure is reported as null once they differ.
+MEASURED_TRAFFIC = {
+    "k_terms_fast<float,10>": {
+        "sources": ["circuits_fast.hip", "wave_state.h", "circuits.h", "common.h"],
+        "sources_sha256": "0c7cf7e3bd788e40", "fetch_kib": 257.0, "write_kib": 2816.0},
+    "k_fwht_fused<6> (n=12 dense)": {
+        "sources": ["decompose.hip", "common.h"],
+        "sources_sha256": "not yet measured", "fetch_kib": 0.0, "write_kib": 0.0},
+}
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131088.4, 1.0
+
+
+def sources_sha256(names) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for nm in names:
+        with open(os.path.join(CSRC, nm), "rb") as f:
+            h.update(nm.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """Scaled HBM bytes per launch of `kernel`, or None when its sources
+    changed after the counters were taken."""
+    m = MEASURED_TRAFFIC[kernel]
+    if sources_sha256(m["sources"]) != m["sources_sha256"]:
+        return None
+    return int(round((m["fetch_kib"] * FETCH_SCALE + m["write_kib"] * WRITE_SCALE) * 1024))
+
+
+def progress(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def circuit_flops(n: int, layers: int) -> int:
@@ -266,17 +305,25 @@ def main() -> int:
     grad = torch.empty((1, P), dtype=torch.float64, device=dev)
 
     ev = []
+    main_s = torch.cuda.current_stream(dev)
+    side_s = torch.cuda.Stream(device=dev)  # default priority
 
     def fast_step(theta, record):
+        # The adjoint gradient and the circuit evaluation both read theta
+        # only: the gradient runs on a second stream beside the circuits,
+        # and the update waits for both.
+        side_s.wait_stream(main_s)
+        with torch.cuda.stream(side_s):
+            api.vqls_grad_adjoint(an, theta, coeffs, strings, "local", "f32", out=(Ca, grad))
         if record:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
+            e0.record(main_s)
         api.vqls_terms(an, theta, strings, "local", "f32", out=(beta, delta))
         if record:
-            e1.record()
+            e1.record(main_s)
             ev.append((e0, e1))
         api.vqls_cost(coeffs, n, "local", beta, delta, out=(C, parts))
-        api.vqls_grad_adjoint(an, theta, coeffs, strings, "local", "f32", out=(Ca, grad))
+        main_s.wait_stream(side_s)
         api.gd_step(theta, grad, ETA)
 
     theta = theta0.clone()
@@ -290,6 +337,7 @@ def main() -> int:
     fast_s = (time.perf_counter() - t0) / args.steps
     kern_ms = sum(a.elapsed_time(b) for a, b in ev) / len(ev)
 
+    progress(f"fast form: {fast_s * 1e3:.3f} ms per iteration")
     # plain form: complex128 circuits + parameter-shift gradient
     ws = api.ShiftWorkspace(an, L, "local", dev)
     Cp = torch.empty(1, dtype=torch.float64, device=dev)
@@ -309,6 +357,7 @@ def main() -> int:
     plain_s = (time.perf_counter() - t0) / args.plain_steps
     plain_circuits = (2 * P + 1) * circuits
 
+    progress(f"plain form: {plain_s * 1e3:.1f} ms per iteration")
     # the prefix-shared execution of the same evaluation (reported separately)
     api.vqls_terms(an, theta0, strings, "local", "f32", exec_="shared", out=(beta, delta))
     torch.cuda.synchronize()
@@ -325,23 +374,26 @@ def main() -> int:
     if not args.no_fwht:
         from workloads import random_symmetric
         A12 = torch.from_numpy(random_symmetric(12, seed=0)).to(dev)
-        c12 = api.pauli_decompose_dense(A12)
+        ws12 = api.decompose_workspace(12, dev)
+        c12 = api.pauli_decompose_dense(A12, workspace=ws12)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         reps = 10
         e0.record()
         for _ in range(reps):
-            api.pauli_decompose_dense(A12)
+            api.pauli_decompose_dense(A12, out=c12, workspace=ws12)
         e1.record()
         torch.cuda.synchronize()
         fwht_ms = e0.elapsed_time(e1) / reps
         alg_bytes = (8 + 16) * 4 ** 12
+        fk = "k_fwht_fused<6> (n=12 dense)"
         fwht = {"bound": "hbm", "achieved": round(alg_bytes / (fwht_ms * 1e-3) / 1e9, 1), "peak": 8000.0,
-                "unit": "GB/s", "frac": round(alg_bytes / (fwht_ms * 1e-3) / 8e12, 4), "traffic": None,
-                "kernel": "k_fwht_pass1 + k_fwht_pass2 (n=12 dense)", "avg_ms": round(fwht_ms, 4),
+                "unit": "GB/s", "frac": round(alg_bytes / (fwht_ms * 1e-3) / 8e12, 4),
+                "traffic": measured_traffic(fk), "kernel": fk, "avg_ms": round(fwht_ms, 4),
                 "algorithmic_bytes": alg_bytes}
-        del A12, c12
+        del A12, c12, ws12
 
+    progress("shared mode and FWHT timed")
     # float32 form vs the float64 path at theta0 (terms, cost, gradient)
     b32, d32 = api.vqls_terms(an, theta0, strings, "local", "f32")
     b64, d64 = api.vqls_terms(an, theta0, strings, "local", "f64")
@@ -360,9 +412,10 @@ def main() -> int:
     flops = circuit_flops(n, layers) * circuits
     achieved = flops / (kern_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_ALU_PEAK,
-                "unit": "TFLOP/s", "frac": round(achieved / FP32_ALU_PEAK, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_ALU_PEAK, 4),
+                "traffic": measured_traffic("k_terms_fast<float,10>"),
                 "kernel": "k_terms_fast<float,10>", "avg_kernel_ms": round(kern_ms, 4),
-                "flops_per_launch": flops}
+                "flops_per_launch": flops, "traffic_unit": "bytes per launch"}
 
     out = {
         "metric": METRIC,
@@ -393,9 +446,11 @@ def main() -> int:
                           "note": "same circuits and results; the ansatz prefix simulated once per wavefront"},
         "roofline_fwht": fwht,
     }
+    progress("precision comparison done")
     if not args.no_warmstart:
         out["warm_start"], out["time_to_solution"] = time_to_solution(
             api, dev, an, coeffs, strings, theta0, fast_s, plain_s, args.tts_budget)
+        progress("warm start and time to solution done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out))

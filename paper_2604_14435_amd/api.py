@@ -59,15 +59,24 @@ def _b_args(b_kind: str, b):
 
 # -------------------------------------------------------------- decomposition
 
-def pauli_decompose_dense(A: torch.Tensor) -> torch.Tensor:
+def decompose_workspace(n: int, device) -> torch.Tensor:
+    """Scratch buffer for pauli_decompose(_dense) at n qubits."""
+    return torch.empty(max(1, L.load().dvq_decompose_workspace_bytes(n)), dtype=torch.uint8, device=device)
+
+
+def pauli_decompose_dense(A: torch.Tensor, out: torch.Tensor | None = None,
+                          workspace: torch.Tensor | None = None) -> torch.Tensor:
     """All 4^n coefficients, complex128 [N, N] indexed [x, z]."""
     A = _cuda(A, torch.float64, "A")
     N = A.shape[0]
     n = N.bit_length() - 1
-    lib = L.load()
-    ws = torch.empty(max(1, lib.dvq_decompose_workspace_bytes(n)), dtype=torch.uint8, device=A.device)
-    out = torch.empty((N, N), dtype=torch.complex128, device=A.device)
-    L.call("dvq_pauli_decompose_dense", _p(A), n, _p(out), _p(ws), ws.numel(), _stream(A))
+    ws = decompose_workspace(n, A.device) if workspace is None else workspace
+    if out is None:
+        out = torch.empty((N, N), dtype=torch.complex128, device=A.device)
+    elif tuple(out.shape) != (N, N) or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous [{N}, {N}] tensor")
+    L.call("dvq_pauli_decompose_dense", _p(A), n, _p(_cuda(out, torch.complex128, "out")), _p(ws), ws.numel(),
+           _stream(A))
     return out
 
 

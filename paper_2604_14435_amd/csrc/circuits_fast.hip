@@ -28,6 +28,10 @@
 // the sign is a per-lane value times a compile-time per-register value.  S is
 // applied to the amplitudes once, when the state leaves the registers.
 //
+// CNOT ladder.  The same kernels run the RY + CNOT-ladder ansatz: the ladder
+// is a permutation, carried as a frame on the registers and applied when
+// the state next goes through LDS (forward_layers_ladder).
+//
 // Suffix.  The state is written to LDS in natural order (with one pad
 // amplitude per 32 to spread banks); the controlled Pauli strings (and X_j)
 // act on the ancilla = 1 half as one permutation with phase:
@@ -42,9 +46,10 @@ namespace dvq {
 
 // The shared prefix of every circuit of one theta row: H on the ancilla and
 // V(theta) on the system register, left in LDS (natural order, padded) with
-// the pending CZ-ladder sign applied.  `trig` receives the rotation
-// parameters phi = theta/2 reduced to [-pi/2, pi/2]: tan(phi/2), sin(phi).
-template <typename T, int NQ>
+// the pending ladder (sign or permutation) applied.  `trig` receives the
+// rotation parameters phi = theta/2 reduced to [-pi/2, pi/2]: tan(phi/2),
+// sin(phi).
+template <typename T, int NQ, int ENT>
 __device__ __forceinline__ void simulate_prefix(const double* __restrict__ theta, int layers,
                                                 cplx<T>* S, T* trig, int lane) {
     constexpr int R = Lay<NQ, false>::R;
@@ -56,11 +61,19 @@ __device__ __forceinline__ void simulate_prefix(const double* __restrict__ theta
         re[r] = (r == 0 && (lane & 31) == 0) ? (T)0.70710678118654752440 : (T)0;
         im[r] = (T)0;
     }
-    forward_layers<T, NQ>(re, im, S, trig, layers, lane);
-    if (layers & 1)
-        store_state<T, NQ, true>(re, im, S, lane, 1);
-    else
-        store_state<T, NQ, false>(re, im, S, lane, 0);
+    if constexpr (ENT == DVQ_ENT_CZ_LADDER) {
+        forward_layers<T, NQ>(re, im, S, trig, layers, lane);
+        if (layers & 1)
+            store_state<T, NQ, true>(re, im, S, lane, 1);
+        else
+            store_state<T, NQ, false>(re, im, S, lane, 0);
+    } else {
+        forward_layers_ladder<T, NQ>(re, im, S, trig, layers, lane);
+        if (layers & 1)
+            store_state_ladder<T, NQ, true>(re, im, S, lane);
+        else
+            store_state_ladder<T, NQ, false>(re, im, S, lane);
+    }
 }
 
 // Controlled U = A_l [X_j] A_m on the ancilla = 1 half as one signed
@@ -132,7 +145,7 @@ __device__ __forceinline__ void measure_suffix_pair(const cplx<T>* S, SignedPerm
 }
 
 // Literal form: one wavefront simulates one circuit, every gate.
-template <typename T, int NQ>
+template <typename T, int NQ, int ENT>
 __global__ void __launch_bounds__(64) k_terms_fast(TermsArgs g) {
     constexpr int N = 1 << NQ;
     constexpr int NSLOT = 2 * N + (2 * N) / 32;
@@ -147,7 +160,7 @@ __global__ void __launch_bounds__(64) k_terms_fast(TermsArgs g) {
     const int64_t row = gid / g.per_row;
     const Term t = decode_term(gid - row * g.per_row, g.L, NQ, g.kind);
 
-    simulate_prefix<T, NQ>(g.theta + row * P, g.layers, S, trig, lane);
+    simulate_prefix<T, NQ, ENT>(g.theta + row * P, g.layers, S, trig, lane);
     const SignedPerm sp = suffix_perm(g.strings[t.l], g.strings[t.m], t.type, t.j);
     const T z = measure_suffix<T, NQ>(S, sp, t.part, lane);
     if (lane == 0) store_term(g, row, t, (double)z);
@@ -157,7 +170,7 @@ __global__ void __launch_bounds__(64) k_terms_fast(TermsArgs g) {
 // once and then the distinct suffix of `chunk` consecutive circuits of the
 // same row (whole Re/Im pairs).  Same results as the literal form; the
 // ansatz work is paid once per chunk instead of once per circuit.
-template <typename T, int NQ>
+template <typename T, int NQ, int ENT>
 __global__ void __launch_bounds__(64) k_terms_shared(TermsArgs g, int64_t chunk, int64_t chunks_per_row) {
     constexpr int N = 1 << NQ;
     constexpr int NSLOT = 2 * N + (2 * N) / 32;
@@ -173,7 +186,7 @@ __global__ void __launch_bounds__(64) k_terms_shared(TermsArgs g, int64_t chunk,
     const int64_t c0 = (wg - row * chunks_per_row) * chunk;
     const int64_t c1 = c0 + chunk < g.per_row ? c0 + chunk : g.per_row;
 
-    simulate_prefix<T, NQ>(g.theta + row * P, g.layers, S, trig, lane);
+    simulate_prefix<T, NQ, ENT>(g.theta + row * P, g.layers, S, trig, lane);
     for (int64_t c = c0; c < c1; c += 2) {
         const Term t = decode_term(c, g.L, NQ, g.kind);
         const SignedPerm sp = suffix_perm(g.strings[t.l], g.strings[t.m], t.type, t.j);
@@ -194,13 +207,19 @@ static size_t fast_lds_bytes(int layers) {
     return (size_t)(2 * N + (2 * N) / 32) * sizeof(cplx<T>) + (size_t)2 * NQ * layers * sizeof(T);
 }
 
-template <typename T, int NQ>
-static dvq_status launch_fast(const TermsArgs& g, hipStream_t s) {
+template <typename T, int NQ, int ENT>
+static dvq_status launch_fast_ent(const TermsArgs& g, hipStream_t s) {
     const size_t lds = fast_lds_bytes<T, NQ>(g.layers);
-    DVQ_TRY_HIP(allow_lds((const void*)k_terms_fast<T, NQ>, lds));
-    hipLaunchKernelGGL((k_terms_fast<T, NQ>), grid_for(g.total), dim3(64), lds, s, g);
+    DVQ_TRY_HIP(allow_lds((const void*)k_terms_fast<T, NQ, ENT>, lds));
+    hipLaunchKernelGGL((k_terms_fast<T, NQ, ENT>), grid_for(g.total), dim3(64), lds, s, g);
     DVQ_CHECK_LAUNCH("k_terms_fast");
     return DVQ_OK;
+}
+
+template <typename T, int NQ>
+static dvq_status launch_fast(const TermsArgs& g, hipStream_t s) {
+    return g.ent == DVQ_ENT_CZ_LADDER ? launch_fast_ent<T, NQ, DVQ_ENT_CZ_LADDER>(g, s)
+                                      : launch_fast_ent<T, NQ, DVQ_ENT_CNOT_LADDER>(g, s);
 }
 
 // Circuits per wavefront in the prefix-shared form: enough wavefronts to
@@ -214,20 +233,25 @@ static int64_t shared_chunk(int64_t per_row, int B) {
     return chunk;
 }
 
-template <typename T, int NQ>
-static dvq_status launch_shared(const TermsArgs& g, hipStream_t s) {
+template <typename T, int NQ, int ENT>
+static dvq_status launch_shared_ent(const TermsArgs& g, hipStream_t s) {
     const size_t lds = fast_lds_bytes<T, NQ>(g.layers);
-    DVQ_TRY_HIP(allow_lds((const void*)k_terms_shared<T, NQ>, lds));
+    DVQ_TRY_HIP(allow_lds((const void*)k_terms_shared<T, NQ, ENT>, lds));
     const int64_t chunk = shared_chunk(g.per_row, g.B);
     const int64_t cpr = (g.per_row + chunk - 1) / chunk;
-    hipLaunchKernelGGL((k_terms_shared<T, NQ>), grid_for(cpr * g.B), dim3(64), lds, s, g, chunk, cpr);
+    hipLaunchKernelGGL((k_terms_shared<T, NQ, ENT>), grid_for(cpr * g.B), dim3(64), lds, s, g, chunk, cpr);
     DVQ_CHECK_LAUNCH("k_terms_shared");
     return DVQ_OK;
 }
 
+template <typename T, int NQ>
+static dvq_status launch_shared(const TermsArgs& g, hipStream_t s) {
+    return g.ent == DVQ_ENT_CZ_LADDER ? launch_shared_ent<T, NQ, DVQ_ENT_CZ_LADDER>(g, s)
+                                      : launch_shared_ent<T, NQ, DVQ_ENT_CNOT_LADDER>(g, s);
+}
+
 static bool fast_shape(const TermsArgs& g) {
-    return g.kind == DVQ_COST_LOCAL && g.bkind == DVQ_B_PLUS && g.ent == DVQ_ENT_CZ_LADDER &&
-           g.n * g.layers <= 1024;
+    return g.kind == DVQ_COST_LOCAL && g.bkind == DVQ_B_PLUS && g.n * g.layers <= 1024;
 }
 
 dvq_status launch_terms_fast(const TermsArgs& g, int precision, hipStream_t s) {

@@ -4,13 +4,16 @@
 // For each x-mask, c[x][z] = (-i)^{|x&z|} / N * sum_k (-1)^{|z&k|} A[k^x][k].
 // The transform over k is split into its low nl = min(n, 6) and high
 // nh = n - nl bits (a Walsh-Hadamard transform is the tensor product of its
-// per-bit butterflies):
+// per-bit butterflies).  For n = 10..12 one fused pass does both parts
+// (k_fwht_fused, below); for n <= 9 two passes run:
 //   pass 1, one workgroup per (xh, kh): the 2^nl x 2^nl tile of A at row
 //     block kh^xh and column block kh is read once, coalesced; for every xl
-//     the xor-diagonal v[kl] = tile[kl^xl][kl] is transformed across the 64
-//     lanes of a wavefront; result T[xh][kh][xl][zl];
+//     the xor-diagonal v[kl] = tile[kl^xl][kl] is transformed in LDS;
+//     result T[xh][kh][xl][zl];
 //   pass 2, one workgroup per x = (xh, xl): T[xh][*][xl][*] is loaded,
-//     transformed over kh across lanes, and c[x][*] written contiguously.
+//     transformed over kh in LDS, and c[x][*] written contiguously.
+// Both forms are bound by HBM traffic: A read once and c written once, plus
+// the intermediate T written and read once in the two-pass form.
 // A is real, so every coefficient is a real number times a power of -i; the
 // selection path stores that real value r = w / N once (8 bytes) and
 // applies the phase only to the kept terms.
@@ -30,16 +33,6 @@ constexpr int kPartials = 1024;
 
 __host__ __device__ constexpr int dec_nl(int n) { return n < 6 ? n : 6; }
 
-// WHT across the first `len` lanes of a wavefront (len a power of two <= 64).
-__device__ __forceinline__ double wave_wht(double v, int len) {
-    const int lane = threadIdx.x & 63;
-    for (int s = 1; s < len; s <<= 1) {
-        const double p = __shfl_xor(v, s, 64);
-        v = (lane & s) ? (p - v) : (v + p);
-    }
-    return v;
-}
-
 __device__ __forceinline__ dvq_c128 phase_mul(double w, uint32_t x, uint32_t z) {
     switch (__popc(x & z) & 3) {  // (-i)^p * w
         case 0: return {w, 0.0};
@@ -49,76 +42,273 @@ __device__ __forceinline__ dvq_c128 phase_mul(double w, uint32_t x, uint32_t z) 
     }
 }
 
-// Pass 1.  If nh == 0 it is the only pass and writes the result itself.
+// In-place Walsh-Hadamard transform of length 2^M of `rows` vectors in LDS,
+// element j of vector r at addr(r, j).  Bits are taken in ascending order,
+// up to three per stage: each task holds the (at most) 8 elements that
+// differ in the stage's bits in registers, so a stage is one LDS read and
+// one LDS write per element and one barrier.
+template <int M, int S, class Addr>
+__device__ __forceinline__ void lds_wht(double* buf, int rows, const Addr& addr) {
+    if constexpr (S < M) {
+        constexpr int B = (M - S) < 3 ? (M - S) : 3;
+        constexpr int R = 1 << B, REST = M - B;
+        const int tasks = rows << REST;
+        for (int t = threadIdx.x; t < tasks; t += blockDim.x) {
+            const int row = t >> REST, rest = t & ((1 << REST) - 1);
+            const int base = (rest & ((1 << S) - 1)) | ((rest >> S) << (S + B));
+            double v[R];
+#pragma unroll
+            for (int u = 0; u < R; ++u) v[u] = buf[addr(row, base | (u << S))];
+#pragma unroll
+            for (int h = 1; h < R; h <<= 1)
+#pragma unroll
+                for (int u = 0; u < R; ++u)
+                    if (!(u & h)) {
+                        const double a = v[u], b = v[u | h];
+                        v[u] = a + b;
+                        v[u | h] = a - b;
+                    }
+#pragma unroll
+            for (int u = 0; u < R; ++u) buf[addr(row, base | (u << S))] = v[u];
+        }
+        __syncthreads();
+        lds_wht<M, S + B>(buf, rows, addr);
+    }
+}
+
+// Pass 1, one workgroup per (xh, kh): the 2^NL x 2^NL tile of A at row
+// block rb = kh^xh and column block kh, all of its loads issued before the first
+// use; the NL-bit transform of every xor-diagonal v_xl[kl] = tile[kl^xl][kl]
+// runs in place.  With nh = n - NL > 0 the result goes to
+// T[xh][kh][xl][zl]; otherwise (n = NL) it is the decomposition itself.
+template <int NL>
 __global__ void __launch_bounds__(kDecThreads)
 k_fwht_pass1(const double* __restrict__ A, int n, double* __restrict__ Tout,
              dvq_c128* __restrict__ dense, double* __restrict__ values) {
-    __shared__ double tile[64 * 65];
-    const int nl = dec_nl(n), nh = n - nl, Nl = 1 << nl, Nh = 1 << nh;
+    constexpr int M = 1 << NL, LD = M + 1, E = M * M;
+    constexpr int EPT = (E + kDecThreads - 1) / kDecThreads;
+    __shared__ double tile[M * LD];
+    const int nh = n - NL;
     const int64_t N = int64_t(1) << n;
-    const int xh = blockIdx.x / Nh, kh = blockIdx.x % Nh;
-    const int rowb = (kh ^ xh) * Nl, colb = kh * Nl;
-    for (int e = threadIdx.x; e < Nl * Nl; e += blockDim.x) {
-        const int r = e / Nl, c = e % Nl;
-        tile[r * 65 + c] = A[(int64_t)(rowb + r) * N + colb + c];
+    // consecutive workgroups take consecutive column blocks of one row
+    // block, so the rows of A are streamed in order
+    const int rb = blockIdx.x >> nh, kh = blockIdx.x & ((1 << nh) - 1), xh = rb ^ kh;
+    const int64_t rowb = (int64_t)rb * M, colb = (int64_t)kh * M;
+    const int64_t tbase = ((int64_t)xh * (1 << nh) + kh) * E;
+    double v[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = i * kDecThreads + threadIdx.x;
+        if (E % kDecThreads == 0 || e < E) v[i] = A[(rowb + e / M) * N + colb + e % M];
+    }
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = i * kDecThreads + threadIdx.x;
+        if (E % kDecThreads == 0 || e < E) tile[(e / M) * LD + e % M] = v[i];
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    lds_wht<NL, 0>(tile, M, [](int xl, int kl) { return (kl ^ xl) * LD + kl; });
     const double invN = 1.0 / (double)N;
-    for (int xl = wid; xl < Nl; xl += kDecThreads / 64) {
-        double v = lane < Nl ? tile[(lane ^ xl) * 65 + lane] : 0.0;
-        v = wave_wht(v, Nl);
-        if (lane < Nl) {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = i * kDecThreads + threadIdx.x;
+        if (E % kDecThreads == 0 || e < E) {
+            const int xl = e >> NL, zl = e & (M - 1);
+            const double w = tile[(zl ^ xl) * LD + zl];
             if (nh > 0) {
-                Tout[((int64_t)(xh * Nh + kh) * Nl + xl) * Nl + lane] = v;
+                Tout[tbase + e] = w;
             } else {
-                const uint32_t x = (uint32_t)xl, z = (uint32_t)lane;
-                if (dense) dense[(int64_t)x * N + z] = phase_mul(v * invN, x, z);
-                if (values) values[(int64_t)x * N + z] = v * invN;
+                if (dense) dense[(int64_t)xl * N + zl] = phase_mul(w * invN, (uint32_t)xl, (uint32_t)zl);
+                if (values) values[(int64_t)xl * N + zl] = w * invN;
             }
         }
     }
 }
 
-// Pass 2 (nh > 0): one workgroup per x-mask.
+// Pass 2 (n = 6 + NH), one workgroup per x-mask x = (xh, xl): the 2^NH
+// segments T[xh][*][xl][*] are loaded, transformed over kh in place, and
+// c[x][*] is written contiguously (z = zh * 64 + zl).
+template <int NH>
 __global__ void __launch_bounds__(kDecThreads)
 k_fwht_pass2(const double* __restrict__ Tin, int n, dvq_c128* __restrict__ dense,
              double* __restrict__ values) {
-    __shared__ double tile[64 * 65];
-    const int nl = dec_nl(n), nh = n - nl, Nl = 1 << nl, Nh = 1 << nh;
+    constexpr int M = 64, LD = M + 1, MH = 1 << NH, E = MH * M;
+    constexpr int EPT = (E + kDecThreads - 1) / kDecThreads;
+    __shared__ double tile[MH * LD];
     const int64_t N = int64_t(1) << n;
     const int x = blockIdx.x;
-    const int xh = x >> nl, xl = x & (Nl - 1);
-    for (int e = threadIdx.x; e < Nh * Nl; e += blockDim.x) {
-        const int kh = e / Nl, zl = e % Nl;
-        tile[kh * 65 + zl] = Tin[((int64_t)(xh * Nh + kh) * Nl + xl) * Nl + zl];
+    const int xh = x >> 6, xl = x & 63;
+    double v[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = i * kDecThreads + threadIdx.x;
+        if (E % kDecThreads == 0 || e < E)
+            v[i] = Tin[((int64_t)(xh * MH + (e >> 6)) * M + xl) * M + (e & 63)];
+    }
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = i * kDecThreads + threadIdx.x;
+        if (E % kDecThreads == 0 || e < E) tile[(e >> 6) * LD + (e & 63)] = v[i];
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int zl = wid; zl < Nl; zl += kDecThreads / 64) {
-        double v = lane < Nh ? tile[lane * 65 + zl] : 0.0;
-        v = wave_wht(v, Nh);
-        if (lane < Nh) tile[lane * 65 + zl] = v;
-    }
-    __syncthreads();
+    lds_wht<NH, 0>(tile, M, [](int zl, int kh) { return kh * LD + zl; });
     const double invN = 1.0 / (double)N;
-    for (int z = threadIdx.x; z < N; z += blockDim.x) {
-        const double w = tile[(z >> nl) * 65 + (z & (Nl - 1))] * invN;
-        if (dense) dense[(int64_t)x * N + z] = phase_mul(w, (uint32_t)x, (uint32_t)z);
-        if (values) values[(int64_t)x * N + z] = w;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int z = i * kDecThreads + threadIdx.x;
+        if (E % kDecThreads == 0 || z < E) {
+            const double w = tile[(z >> 6) * LD + (z & 63)] * invN;
+            if (dense) dense[(int64_t)x * N + z] = phase_mul(w, (uint32_t)x, (uint32_t)z);
+            if (values) values[(int64_t)x * N + z] = w;
+        }
     }
+}
+
+// Single pass for n = 6 + NH, NH = 4..6 (n = 10..12): the intermediate T
+// never leaves the chip.  One workgroup of 128 XB threads per (xh, a), where
+// a selects the XB consecutive x-masks xl = XB a + b (b < XB).  In tile
+// (kh^xh, kh) the elements of these XB xor-diagonals are, in every row r,
+// the XB contiguous columns XB ((r / XB) ^ a) + 0..XB-1, so the workgroups
+// of one xh read the 2^NH tiles exactly once between them.  Tiles are taken
+// in batches of eight (kh = 8 kh1 + kh0), the next batch's loads in flight
+// while one is transformed: each batch's 8 XB diagonals (kh0, b) are
+// transformed over kl in LDS; each thread (b, half, zl) then takes the
+// eight values T[kh0][b][zl], transforms them over kh0 in registers, and
+// accumulates them with the sign
+// (-1)^{|zh1 & kh1|} into its 2^(NH-1) outputs zh = 8 zh1 + zh0 (zh1 in its
+// half of the range).  The transform over kh is therefore the same
+// Walsh-Hadamard sum, split into an 8-point fast part and a direct part.
+// The outputs are written with non-temporal stores (nothing here reads them
+// again), which leaves L2 to the shared input lines.  XB = 2 (256 threads,
+// eight workgroups per 128-byte line, 4 workgroups per CU) measured fastest
+// of XB = 1, 2, 4, 8 on MI355X.
+template <int NH, int XB>
+__global__ void __launch_bounds__(128 * XB, 4)
+k_fwht_fused(const double* __restrict__ A, int n, dvq_c128* __restrict__ dense,
+             double* __restrict__ values) {
+    constexpr int THREADS = 128 * XB, MH = 1 << NH, NB = MH / 8, ZH1 = NB / 2, ACC = 8 * ZH1, LD = 65;
+    constexpr int EPT = 8 * 64 * XB / THREADS;  // batch elements per thread (4)
+    constexpr int SHARE = 16 / XB;              // workgroups reading one 128-byte line
+    __shared__ double d[8 * XB * LD];           // row kh0 * XB + b, column kl
+    const int64_t N = int64_t(1) << n;
+    // The SHARE workgroups that read the parts of the same 128-byte lines
+    // are placed 8 apart: workgroups go to the 8 XCDs round robin (blockIdx
+    // mod 8), so they run on one XCD, one after another, and all but the
+    // first read of each line is served by that XCD's L2.
+    const int c = blockIdx.x & 7, sq = blockIdx.x >> 3;
+    const int grp = (sq / SHARE) * 8 + c;
+    const int xh = grp >> 2, a = SHARE * (grp & 3) + sq % SHARE;
+    const int t = threadIdx.x, zl = t & 63, b = t >> 7, half = (t >> 6) & 1;
+
+    auto load = [&](double* v, int kh1) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = i * THREADS + t;
+            const int kh = kh1 * 8 + e / (64 * XB), r = (e / XB) & 63, cl = e & (XB - 1);
+            v[i] = A[((int64_t)(kh ^ xh) * 64 + r) * N + (int64_t)kh * 64 + XB * ((r / XB) ^ a) + cl];
+        }
+    };
+    double v[EPT];
+    double acc[ACC];
+#pragma unroll
+    for (int i = 0; i < ACC; ++i) acc[i] = 0.0;
+    load(v, 0);
+#pragma unroll 1
+    for (int kh1 = 0; kh1 < NB; ++kh1) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = i * THREADS + t;
+            const int kh0 = e / (64 * XB), r = (e / XB) & 63, cl = e & (XB - 1);
+            const int kl = XB * ((r / XB) ^ a) + cl, bb = (r & (XB - 1)) ^ cl;
+            d[(kh0 * XB + bb) * LD + kl] = v[i];
+        }
+        if (kh1 + 1 < NB) load(v, kh1 + 1);
+        __syncthreads();
+        lds_wht<6, 0>(d, 8 * XB, [](int row, int kl) { return row * LD + kl; });  // ends with a barrier
+        double u[8];
+#pragma unroll
+        for (int k0 = 0; k0 < 8; ++k0) u[k0] = d[(k0 * XB + b) * LD + zl];
+#pragma unroll
+        for (int h = 1; h < 8; h <<= 1)
+#pragma unroll
+            for (int k0 = 0; k0 < 8; ++k0)
+                if (!(k0 & h)) {
+                    const double p = u[k0], q = u[k0 | h];
+                    u[k0] = p + q;
+                    u[k0 | h] = p - q;
+                }
+#pragma unroll
+        for (int j = 0; j < ZH1; ++j) {
+            const bool neg = __popc((unsigned)((half * ZH1 + j) & kh1)) & 1;
+#pragma unroll
+            for (int z0 = 0; z0 < 8; ++z0) acc[j * 8 + z0] += neg ? -u[z0] : u[z0];
+        }
+        __syncthreads();
+    }
+    const double invN = 1.0 / (double)N;
+    const uint32_t x = (uint32_t)(xh * 64 + a * XB + b);
+#pragma unroll
+    for (int j = 0; j < ZH1; ++j)
+#pragma unroll
+        for (int z0 = 0; z0 < 8; ++z0) {
+            const uint32_t z = (uint32_t)(((half * ZH1 + j) * 8 + z0) * 64 + zl);
+            const double w = acc[j * 8 + z0] * invN;
+            if (dense) {
+                typedef double d2 __attribute__((ext_vector_type(2)));
+                const dvq_c128 cz = phase_mul(w, x, z);
+                __builtin_nontemporal_store(d2{cz.re, cz.im}, reinterpret_cast<d2*>(dense + (int64_t)x * N + z));
+            }
+            if (values) __builtin_nontemporal_store(w, values + (int64_t)x * N + z);
+        }
+}
+
+template <int NH, int XB = 2>
+static void launch_fused(const double* A, int n, dvq_c128* dense, double* values, hipStream_t s) {
+    hipLaunchKernelGGL((k_fwht_fused<NH, XB>), dim3((64 / XB) << NH), dim3(128 * XB), 0, s, A, n, dense, values);
+}
+
+// n for which the decomposition runs as the single fused pass.
+__host__ __device__ constexpr bool fwht_fused(int n) { return n >= 10 && n <= 12; }
+
+template <int NL>
+static void launch_pass1(const double* A, int n, double* T, dvq_c128* dense, double* values, hipStream_t s) {
+    hipLaunchKernelGGL(k_fwht_pass1<NL>, dim3(1u << (2 * (n - NL))), dim3(kDecThreads), 0, s, A, n, T, dense,
+                       values);
+}
+
+template <int NH>
+static void launch_pass2(const double* T, int n, dvq_c128* dense, double* values, hipStream_t s) {
+    hipLaunchKernelGGL(k_fwht_pass2<NH>, dim3(1u << n), dim3(kDecThreads), 0, s, T, n, dense, values);
 }
 
 static dvq_status run_fwht(const double* A, int n, double* T, dvq_c128* dense, double* values,
                            hipStream_t s) {
-    const int nl = dec_nl(n), nh = n - nl;
-    const int tiles = 1 << (2 * nh);
-    hipLaunchKernelGGL(k_fwht_pass1, dim3(tiles), dim3(kDecThreads), 0, s, A, n, T, dense, values);
-    DVQ_CHECK_LAUNCH("k_fwht_pass1");
-    if (nh > 0) {
-        hipLaunchKernelGGL(k_fwht_pass2, dim3(1 << n), dim3(kDecThreads), 0, s, T, n, dense, values);
-        DVQ_CHECK_LAUNCH("k_fwht_pass2");
+    if (fwht_fused(n)) {
+        if (n == 10) launch_fused<4>(A, n, dense, values, s);
+        else if (n == 11) launch_fused<5>(A, n, dense, values, s);
+        else launch_fused<6>(A, n, dense, values, s);
+        DVQ_CHECK_LAUNCH("k_fwht_fused");
+        return DVQ_OK;
     }
+    switch (dec_nl(n)) {
+        case 1: launch_pass1<1>(A, n, T, dense, values, s); break;
+        case 2: launch_pass1<2>(A, n, T, dense, values, s); break;
+        case 3: launch_pass1<3>(A, n, T, dense, values, s); break;
+        case 4: launch_pass1<4>(A, n, T, dense, values, s); break;
+        case 5: launch_pass1<5>(A, n, T, dense, values, s); break;
+        default: launch_pass1<6>(A, n, T, dense, values, s); break;
+    }
+    DVQ_CHECK_LAUNCH("k_fwht_pass1");
+    switch (n - dec_nl(n)) {
+        case 0: return DVQ_OK;
+        case 1: launch_pass2<1>(T, n, dense, values, s); break;
+        case 2: launch_pass2<2>(T, n, dense, values, s); break;
+        case 3: launch_pass2<3>(T, n, dense, values, s); break;
+        case 4: launch_pass2<4>(T, n, dense, values, s); break;
+        case 5: launch_pass2<5>(T, n, dense, values, s); break;
+        default: launch_pass2<6>(T, n, dense, values, s); break;
+    }
+    DVQ_CHECK_LAUNCH("k_fwht_pass2");
     return DVQ_OK;
 }
 
@@ -317,7 +507,7 @@ static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 static size_t dec_ws_layout(int n, DecWs* ws, void* base) {
     const size_t total = size_t(1) << (2 * n);
-    const bool two_pass = n > 6;
+    const bool two_pass = n > 6 && !fwht_fused(n);
     size_t off = 0;
     auto take = [&](size_t bytes) -> char* {
         char* p = base ? static_cast<char*>(base) + off : nullptr;

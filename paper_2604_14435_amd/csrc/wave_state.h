@@ -17,6 +17,18 @@
 // far, mod 2).  S RY_q S rotates by (-1)^{g_{q-1} xor g_{q+1}} t on each pair,
 // so with p = 1 every pair uses +-angle: a per-lane sign times a
 // compile-time per-register sign.
+//
+// CNOT ladder.  CNOT(q -> q+1) for q = 0..NQ-2 in order maps basis index k
+// to its prefix parity: bit j of pi(k) is the parity of bits 0..j of k.
+// After a ladder the registers are left in the ladder frame (stored index k
+// holds the true amplitude of pi(k)) and the next relayout writes each
+// amplitude to LDS slot pi(k), which returns to the true frame at no cost.
+// In the ladder frame, RY on true qubit q pairs k with
+// pi^-1(pi(k) ^ 2^q) = k ^ 2^q ^ 2^{q+1} (k ^ 2^q for the last qubit), and
+// the member with bit q clear is the true |0> member iff bits 0..q-1 of k
+// have even parity (else the pair turns by -angle).  Both bits are register
+// bits for every qubit of the HI layout and for qubits 0..RB-2 of LO; qubit
+// RB-1 of LO pairs register bit RB-1 with lane bit 0, a DPP lane swap.
 #pragma once
 
 #include "circuits.h"
@@ -35,11 +47,13 @@ struct Lay {
     static constexpr int lanebit(int q) {
         return HI ? ((q >= 0 && q < 5) ? q : -1) : ((q >= RB && q < NQ) ? q - RB : -1);
     }
-    // global basis index of (lane, r); bit NQ is the half
-    __device__ static __forceinline__ int g(int lane, int r) {
-        return HI ? ((lane & 31) | (r << 5) | ((lane >> 5) << NQ))
-                  : (r | ((lane & 31) << RB) | ((lane >> 5) << NQ));
+    // global basis index of (lane, r); bit NQ is the half.  The lane and
+    // register parts occupy disjoint bits: g = glane(lane) | greg(r).
+    __device__ static __forceinline__ int glane(int lane) {
+        return HI ? ((lane & 31) | ((lane >> 5) << NQ)) : (((lane & 31) << RB) | ((lane >> 5) << NQ));
     }
+    __host__ __device__ static constexpr int greg(int r) { return HI ? (r << 5) : r; }
+    __device__ static __forceinline__ int g(int lane, int r) { return glane(lane) | greg(r); }
 };
 
 // LDS slot of basis index g: one pad amplitude every 32.
@@ -126,6 +140,198 @@ __device__ __forceinline__ void relayout(T* re, T* im, cplx<T>* S, int lane) {
         im[r] = v.im;
     }
     __syncthreads();
+}
+
+// ---------------------------------------------------------------- CNOT ladder
+
+// pi on the NQ system bits of g (bit NQ, the half, is kept); linear over
+// GF(2), so pi(glane ^ greg) = pi(glane) ^ pi(greg).
+template <int NQ>
+__host__ __device__ constexpr int ladder_perm(int g) {
+    static_assert(NQ <= 16, "prefix parity over at most 16 bits");
+    constexpr int M = (1 << NQ) - 1;
+    int y = g & M;
+    y ^= y << 1;
+    y ^= y << 2;
+    y ^= y << 4;
+    y ^= y << 8;
+    return (y & M) | (g & ~M);
+}
+
+__host__ __device__ constexpr bool odd_bits(int v) {
+    bool p = false;
+    for (; v; v &= v - 1) p = !p;
+    return p;
+}
+
+// RY on true qubit Q with the registers in the ladder frame (both bits of
+// the stored pair in registers).
+template <typename T, int NQ, bool HI, int Q>
+__device__ __forceinline__ void ry_reg_ladder(T* re, T* im, int lane, T t, T s) {
+    using Ly = Lay<NQ, HI>;
+    constexpr int R = Ly::R;
+    constexpr int j = Ly::reg(Q);
+    constexpr int jp = Q + 1 < NQ ? Ly::reg(Q + 1) : -1;
+    static_assert(j >= 0 && (Q + 1 == NQ || jp >= 0), "pair not in registers");
+    constexpr int mask = (1 << j) | (jp >= 0 ? (1 << jp) : 0);
+    // register bits that hold the qubits below Q (lane bits hold the rest in HI)
+    constexpr int low = HI ? ((1 << (Q - 5)) - 1) : ((1 << Q) - 1);
+    T tp = t, sp = s;
+    if constexpr (HI) {
+        if (__popc((unsigned)(lane & 31)) & 1) {
+            tp = -t;
+            sp = -s;
+        }
+    }
+    const T mtp = -tp, mtn = tp, spp = sp, spn = -sp;
+#pragma unroll
+    for (int r0 = 0; r0 < R; ++r0) {
+        if (r0 & (1 << j)) continue;
+        const int r1 = r0 ^ mask;
+        const bool neg = odd_bits(r0 & low);
+        const T mt = neg ? mtn : mtp;
+        const T ss = neg ? spn : spp;
+        re[r0] = fmat(mt, re[r1], re[r0]);
+        im[r0] = fmat(mt, im[r1], im[r0]);
+        re[r1] = fmat(ss, re[r0], re[r1]);
+        im[r1] = fmat(ss, im[r0], im[r1]);
+        re[r0] = fmat(mt, re[r1], re[r0]);
+        im[r0] = fmat(mt, im[r1], im[r0]);
+    }
+}
+
+template <typename T, int NQ, bool HI, int Q, int QEND>
+__device__ __forceinline__ void ry_range_ladder(T* re, T* im, int lane, const T* trig, int kbase) {
+    if constexpr (Q < QEND) {
+        ry_reg_ladder<T, NQ, HI, Q>(re, im, lane, trig[2 * (kbase + Q)], trig[2 * (kbase + Q) + 1]);
+        ry_range_ladder<T, NQ, HI, Q + 1, QEND>(re, im, lane, trig, kbase);
+    }
+}
+
+// Value held by lane ^ 1 (DPP quad permutation [1, 0, 3, 2]).
+__device__ __forceinline__ float lane_xor1(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ double lane_xor1(double x) {
+    const long long u = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)u, 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), 0xB1, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// RY on true qubit RB-1 in layout LO, ladder frame: the stored partner of
+// (lane, r) is (lane ^ 1, r ^ 2^(RB-1)); bits 0..RB-1 of k are the register
+// bits, so the amplitude is the true |1> member iff r has odd parity.
+// Direct form: x' = cos(phi) x -+ sin(phi) p.
+template <typename T, int NQ>
+__device__ __forceinline__ void ry_lane_ladder_lo(T* re, T* im, T t, T s) {
+    using Ly = Lay<NQ, false>;
+    constexpr int R = Ly::R, j = Ly::RB - 1;
+    static_assert(Ly::lanebit(Ly::RB) == 0, "qubit RB must sit in lane bit 0");
+    const T c = fmat(-t, s, (T)1);  // cos(phi) = 1 - tan(phi/2) sin(phi)
+#pragma unroll
+    for (int r0 = 0; r0 < R; ++r0) {
+        if (r0 & (1 << j)) continue;
+        const int r1 = r0 | (1 << j);
+        const T p0r = lane_xor1(re[r1]), p0i = lane_xor1(im[r1]);  // partner of r0
+        const T p1r = lane_xor1(re[r0]), p1i = lane_xor1(im[r0]);  // partner of r1
+        const T s0 = odd_bits(r0) ? s : -s, s1 = odd_bits(r1) ? s : -s;
+        re[r0] = fmat(s0, p0r, c * re[r0]);
+        im[r0] = fmat(s0, p0i, c * im[r0]);
+        re[r1] = fmat(s1, p1r, c * re[r1]);
+        im[r1] = fmat(s1, p1i, c * im[r1]);
+    }
+}
+
+// pi^-1(m) = m ^ (m << 1) on the system bits.
+template <int NQ>
+__host__ __device__ constexpr int ladder_unperm(int m) {
+    constexpr int M = (1 << NQ) - 1;
+    return ((m ^ (m << 1)) & M) | (m & ~M);
+}
+
+// Layout swap that also leaves the ladder frame: the amplitudes are written
+// in stored order and each (lane, r) of the other layout reads its true
+// index m from slot pi^-1(m).  The lane and register parts of pi^-1 overlap
+// in one bit (RB for LO, 5 for HI), so every read is one of two per-lane
+// bases plus a compile-time offset.
+template <typename T, int NQ, bool FROM_HI>
+__device__ __forceinline__ void relayout_ladder(T* re, T* im, cplx<T>* S, int lane) {
+    using From = Lay<NQ, FROM_HI>;
+    using To = Lay<NQ, !FROM_HI>;
+    constexpr int R = From::R;
+    constexpr int SPLIT = FROM_HI ? To::RB : 5;
+#pragma unroll
+    for (int r = 0; r < R; ++r) S[pad_slot(From::g(lane, r))] = {re[r], im[r]};
+    __syncthreads();
+    const int ub = ladder_unperm<NQ>(To::glane(lane));
+    const int base0 = pad_slot(ub), base1 = pad_slot(ub ^ (1 << SPLIT));
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int u = ladder_unperm<NQ>(To::greg(r));
+        const int off = u & ~(1 << SPLIT);
+        const cplx<T> v = S[((u >> SPLIT) & 1 ? base1 : base0) + off + (off >> 5)];
+        re[r] = v.re;
+        im[r] = v.im;
+    }
+    __syncthreads();
+}
+
+// Write the registers (ladder frame) to LDS in natural order: slot pi(k).
+// In LO, pi of the register part is prefix(r) in bits 0..RB-1 and the
+// parity of r in every higher bit, so again two bases and an offset; HI
+// first swaps to LO through relayout_ladder.
+template <typename T, int NQ, bool HI>
+__device__ __forceinline__ void store_state_ladder(T* re, T* im, cplx<T>* S, int lane) {
+    using Lo = Lay<NQ, false>;
+    constexpr int R = Lo::R, RB = Lo::RB;
+    constexpr int HM = ((1 << NQ) - 1) & ~((1 << RB) - 1);
+    if constexpr (HI) relayout_ladder<T, NQ, true>(re, im, S, lane);
+    if constexpr (HI) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) S[pad_slot(Lo::g(lane, r))] = {re[r], im[r]};
+    } else {
+        const int pl = ladder_perm<NQ>(Lo::glane(lane));
+        const int base0 = pad_slot(pl), base1 = pad_slot(pl ^ HM);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int off = ladder_perm<NQ>(r) & ((1 << RB) - 1);
+            S[(odd_bits(r) ? base1 : base0) + off + (off >> 5)] = {re[r], im[r]};
+        }
+    }
+    __syncthreads();
+}
+
+// Forward pass of the RY + CNOT-ladder ansatz, starting in LO (true frame).
+// Layer 0 runs as in the CZ form; a layer that starts in HI (odd) turns
+// qubits 5..NQ-1 in the ladder frame, swaps to LO (true frame) and turns
+// qubits 0..4; a later layer that starts in LO turns qubits 0..RB-2 in the
+// ladder frame, qubit RB-1 too when it is 4 (lane swap), swaps to HI and
+// turns the rest.  Ends in the ladder frame, in LO (layers even) or HI.
+template <typename T, int NQ>
+__device__ __forceinline__ void forward_layers_ladder(T* re, T* im, cplx<T>* S, const T* trig, int layers,
+                                                      int lane) {
+    constexpr int RB = Lay<NQ, false>::RB;
+    ry_range<T, NQ, false, 0, 0, NQ>(re, im, lane, trig, 0);
+    relayout<T, NQ, false>(re, im, S, lane);
+    ry_range<T, NQ, true, 0, RB, NQ>(re, im, lane, trig, 0);
+    int l = 1;
+    for (; l < layers; l += 2) {
+        // odd layer l: starts in HI
+        int kb = l * NQ;
+        ry_range_ladder<T, NQ, true, 5, NQ>(re, im, lane, trig, kb);
+        relayout_ladder<T, NQ, true>(re, im, S, lane);
+        ry_range<T, NQ, false, 0, 0, 5>(re, im, lane, trig, kb);
+        if (l + 1 >= layers) break;
+        // even layer l + 1: starts in LO
+        kb += NQ;
+        ry_range_ladder<T, NQ, false, 0, RB - 1>(re, im, lane, trig, kb);
+        if constexpr (RB - 1 < 5)
+            ry_lane_ladder_lo<T, NQ>(re, im, trig[2 * (kb + RB - 1)], trig[2 * (kb + RB - 1) + 1]);
+        relayout_ladder<T, NQ, false>(re, im, S, lane);
+        ry_range<T, NQ, true, 0, 5, NQ>(re, im, lane, trig, kb);
+    }
 }
 
 template <int NQ>

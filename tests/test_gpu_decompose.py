@@ -28,8 +28,10 @@ def _flat(strings, n):
     return s[:, 0] * (1 << n) + s[:, 1]
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 5, 6, 7, 8])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 6, 7, 8, 9, 10, 11])
 def test_dense_matches_oracle_random(n):
+    """Every coefficient; n <= 9 runs the tiled two-pass transform, n = 10, 11
+    the single fused pass."""
     A = random_symmetric(n, seed=n)
     A[0, -1] += 0.3  # break the symmetry: odd-Y strings become nonzero
     got = api.pauli_decompose_dense(_gpu(A)).cpu().numpy()

@@ -134,20 +134,22 @@ def test_bit_reproducible():
         assert torch.equal(b1, b2) and torch.equal(o1, o2)
 
 
+@pytest.mark.parametrize("ent", ["cz", "cnot"])
 @pytest.mark.parametrize("n,layers,precision", [(10, 1, "f32"), (10, 3, "f64"), (10, 5, "f32"),
-                                                (10, 6, "f64"), (11, 2, "f32"), (11, 3, "f32")])
-def test_wavefront_kernel_shapes(n, layers, precision):
-    """The register-resident kernel (n = 10, 11): even and odd layer counts,
-    a ragged L = 7 with x = 0 strings, odd Y counts and every j; sampled
-    terms against the oracle's circuits, and the full output against the
-    generic LDS kernel."""
+                                                (10, 6, "f64"), (11, 2, "f32"), (11, 3, "f32"),
+                                                (11, 4, "f32"), (10, 4, "f32")])
+def test_wavefront_kernel_shapes(n, layers, precision, ent):
+    """The register-resident kernel (n = 10, 11) with either ladder: even and
+    odd layer counts, a ragged L = 7 with x = 0 strings, odd Y counts and
+    every j; sampled terms against the oracle's circuits, and the full output
+    against the generic LDS kernel."""
     rng = np.random.default_rng(n * 10 + layers)
     N = 1 << n
     strings = rng.integers(0, N, size=(7, 2)).astype(np.int32)
     strings[0] = (0, 0)
     strings[1, 0] = 0
     th = rng.uniform(0, 2 * math.pi, size=(2, n * layers))
-    an = api.AnsatzSpec(n, layers, "cz")
+    an = api.AnsatzSpec(n, layers, ent)
     beta, delta = api.vqls_terms(an, _gpu(th), _gpu(strings), "local", precision)
     gb, gd = api.vqls_terms(an, _gpu(th), _gpu(strings), "local", precision, exec_="generic")
     tol = TOL[precision]
@@ -158,13 +160,14 @@ def test_wavefront_kernel_shapes(n, layers, precision):
         for _ in range(4):
             l, m = (int(v) for v in rng.integers(0, 7, 2))
             sl, sm = (int(strings[l, 0]), int(strings[l, 1])), (int(strings[m, 0]), int(strings[m, 1]))
-            assert abs(beta[r, l, m] - qc.beta_term(th[r], n, layers, "cz", sl, sm)) < tol
+            assert abs(beta[r, l, m] - qc.beta_term(th[r], n, layers, ent, sl, sm)) < tol
             j = int(rng.integers(0, n))
-            assert abs(delta[r, j, l, m] - qc.delta_term(th[r], n, layers, "cz", sl, sm, j)) < tol
+            assert abs(delta[r, j, l, m] - qc.delta_term(th[r], n, layers, ent, sl, sm, j)) < tol
 
 
+@pytest.mark.parametrize("ent", ["cz", "cnot"])
 @pytest.mark.parametrize("n,layers,precision", [(10, 4, "f32"), (10, 3, "f64"), (11, 2, "f32")])
-def test_prefix_shared_mode(n, layers, precision):
+def test_prefix_shared_mode(n, layers, precision, ent):
     """Prefix-shared execution (ansatz once per wavefront, each circuit's own
     gates on a copy): B = 3 rows, ragged L = 9; sampled terms against the
     oracle's circuits and every term against the literal kernel."""
@@ -173,7 +176,7 @@ def test_prefix_shared_mode(n, layers, precision):
     strings = rng.integers(0, N, size=(9, 2)).astype(np.int32)
     strings[2] = (0, 0)
     th = rng.uniform(0, 2 * math.pi, size=(3, n * layers))
-    an = api.AnsatzSpec(n, layers, "cz")
+    an = api.AnsatzSpec(n, layers, ent)
     bs, ds = api.vqls_terms(an, _gpu(th), _gpu(strings), "local", precision, exec_="shared")
     bl, dl = api.vqls_terms(an, _gpu(th), _gpu(strings), "local", precision, exec_="literal")
     tol = TOL[precision]
@@ -184,6 +187,6 @@ def test_prefix_shared_mode(n, layers, precision):
         for _ in range(3):
             l, m = (int(v) for v in rng.integers(0, 9, 2))
             sl, sm = (int(strings[l, 0]), int(strings[l, 1])), (int(strings[m, 0]), int(strings[m, 1]))
-            assert abs(bs[r, l, m] - qc.beta_term(th[r], n, layers, "cz", sl, sm)) < tol
+            assert abs(bs[r, l, m] - qc.beta_term(th[r], n, layers, ent, sl, sm)) < tol
             j = int(rng.integers(0, n))
-            assert abs(ds[r, j, l, m] - qc.delta_term(th[r], n, layers, "cz", sl, sm, j)) < tol
+            assert abs(ds[r, j, l, m] - qc.delta_term(th[r], n, layers, ent, sl, sm, j)) < tol
