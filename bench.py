@@ -41,12 +41,12 @@ CSRC = os.path.join(ROOT, "paper_2604_14435_amd", "csrc")
 # Valid only for the kernel sources they were taken on: `sources_sha256` is
 # checked at run time and the figure is reported as null once they differ.
 MEASURED_TRAFFIC = {
-    "k_terms_fast<float,10>": {
+    "k_terms_fast<float,10,cz>": {
         "sources": ["circuits_fast.hip", "wave_state.h", "circuits.h", "common.h"],
-        "sources_sha256": "0c7cf7e3bd788e40", "fetch_kib": 257.0, "write_kib": 2816.0},
-    "k_fwht_fused<6> (n=12 dense)": {
+        "sources_sha256": "8df9cc9d91ffebf1", "fetch_kib": 252.1, "write_kib": 2816.0},
+    "k_fwht_fused<6,2> (n=12 dense)": {
         "sources": ["decompose.hip", "common.h"],
-        "sources_sha256": "not yet measured", "fetch_kib": 0.0, "write_kib": 0.0},
+        "sources_sha256": "a4a7ec1ef26ff715", "fetch_kib": 66005.5, "write_kib": 262222.2},
 }
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131088.4, 1.0
 
@@ -386,7 +386,7 @@ def main() -> int:
         torch.cuda.synchronize()
         fwht_ms = e0.elapsed_time(e1) / reps
         alg_bytes = (8 + 16) * 4 ** 12
-        fk = "k_fwht_fused<6> (n=12 dense)"
+        fk = "k_fwht_fused<6,2> (n=12 dense)"
         fwht = {"bound": "hbm", "achieved": round(alg_bytes / (fwht_ms * 1e-3) / 1e9, 1), "peak": 8000.0,
                 "unit": "GB/s", "frac": round(alg_bytes / (fwht_ms * 1e-3) / 8e12, 4),
                 "traffic": measured_traffic(fk), "kernel": fk, "avg_ms": round(fwht_ms, 4),
@@ -413,8 +413,8 @@ def main() -> int:
     achieved = flops / (kern_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_ALU_PEAK,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_ALU_PEAK, 4),
-                "traffic": measured_traffic("k_terms_fast<float,10>"),
-                "kernel": "k_terms_fast<float,10>", "avg_kernel_ms": round(kern_ms, 4),
+                "traffic": measured_traffic("k_terms_fast<float,10,cz>"),
+                "kernel": "k_terms_fast<float,10,cz>", "avg_kernel_ms": round(kern_ms, 4),
                 "flops_per_launch": flops, "traffic_unit": "bytes per launch"}
 
     out = {

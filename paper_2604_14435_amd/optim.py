@@ -1,0 +1,123 @@
+"""L-BFGS-B driver for one VQLS system (the paper's optimizer, Section III).
+
+The optimizer itself is host-side (SciPy's L-BFGS-B on the P angles, as in
+the paper); every cost and gradient it asks for is computed on the GPU by
+libdvq.so:
+  * fast form  ("f32"): the cost from the 2(n+1)L^2 Hadamard-test circuits
+    with complex64 states (float64 accumulation), the gradient from the
+    adjoint sweep with complex64 states, the two launched on separate
+    streams;
+  * plain form ("f64"): cost and gradient from the parameter-shift rule,
+    (2P + 1) evaluations of every circuit with complex128 states;
+  * adjoint form ("f64-adjoint"): cost and gradient from the complex128
+    adjoint sweep (same values as the plain form to rounding: the shift rule
+    is exact for RY gates).
+Each evaluation ends with one device-to-host copy of (cost, gradient).
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import api
+
+
+@dataclass
+class Trace:
+    """What one run did: costs per evaluation, iterates per iteration."""
+    costs: list = field(default_factory=list)      # every evaluation
+    thetas: list = field(default_factory=list)     # accepted iterates (L-BFGS iterations)
+    evals: int = 0
+    seconds: float = 0.0
+    stop: str = ""
+
+
+class Evaluator:
+    """Cost and gradient of one system at one angle vector, on the GPU."""
+
+    def __init__(self, ansatz: api.AnsatzSpec, coeffs: torch.Tensor, strings: torch.Tensor, form: str,
+                 kind: str = "local", b_kind: str = "plus", b=None):
+        if form not in ("f32", "f64", "f64-adjoint"):
+            raise ValueError(f"unknown form {form!r}")
+        self.an, self.coeffs, self.strings, self.form = ansatz, coeffs, strings, form
+        self.kind, self.b_kind, self.b = kind, b_kind, b
+        dev = coeffs.device
+        self.dev = dev
+        L = coeffs.shape[0]
+        n, P = ansatz.n, ansatz.P
+        self.theta = torch.empty((1, P), dtype=torch.float64, device=dev)
+        self.C = torch.empty(1, dtype=torch.float64, device=dev)
+        self.g = torch.empty((1, P), dtype=torch.float64, device=dev)
+        self.Ca = torch.empty(1, dtype=torch.float64, device=dev)
+        self.out_host = torch.empty(P + 1, dtype=torch.float64, pin_memory=True)
+        self.packed = torch.empty(P + 1, dtype=torch.float64, device=dev)
+        if form == "f32":
+            other = (1, n, L, L) if kind == "local" else (1, L)
+            self.beta = torch.empty((1, L, L), dtype=torch.complex128, device=dev)
+            self.other = torch.empty(other, dtype=torch.complex128, device=dev)
+            self.parts = torch.empty((1, 2), dtype=torch.complex128, device=dev)
+            self.side = torch.cuda.Stream(device=dev)  # default priority
+        elif form == "f64":
+            self.ws = api.ShiftWorkspace(ansatz, L, kind, dev)
+
+    def __call__(self, theta: np.ndarray) -> tuple[float, np.ndarray]:
+        main = torch.cuda.current_stream(self.dev)
+        self.theta.copy_(torch.from_numpy(np.asarray(theta, dtype=np.float64)).view(1, -1))
+        if self.form == "f32":
+            self.side.wait_stream(main)
+            with torch.cuda.stream(self.side):
+                api.vqls_grad_adjoint(self.an, self.theta, self.coeffs, self.strings, self.kind, "f32",
+                                      b_kind=self.b_kind, b=self.b, out=(self.Ca, self.g))
+            api.vqls_terms(self.an, self.theta, self.strings, self.kind, "f32", b_kind=self.b_kind, b=self.b,
+                           out=(self.beta, self.other))
+            api.vqls_cost(self.coeffs, self.an.n, self.kind, self.beta, self.other, out=(self.C, self.parts))
+            main.wait_stream(self.side)
+        elif self.form == "f64":
+            api.vqls_grad_shift(self.an, self.theta[0], self.coeffs, self.strings, self.kind, "f64",
+                                b_kind=self.b_kind, b=self.b, workspace=self.ws, out=(self.C, self.g[0]))
+        else:
+            api.vqls_grad_adjoint(self.an, self.theta, self.coeffs, self.strings, self.kind, "f64",
+                                  b_kind=self.b_kind, b=self.b, out=(self.C, self.g))
+        self.packed[0:1].copy_(self.C)
+        self.packed[1:].copy_(self.g[0])
+        self.out_host.copy_(self.packed)  # synchronous: waits for the evaluation
+        v = self.out_host.numpy()
+        return float(v[0]), v[1:].copy()
+
+
+def lbfgs(evaluate, theta0: np.ndarray, max_evals: int = 2000, target: float | None = None,
+          gtol: float = 1e-9, ftol: float = 1e-15, memory: int = 10) -> tuple[np.ndarray, Trace]:
+    """Minimise with L-BFGS-B from theta0.  Stops at convergence, after
+    `max_evals` evaluations, or as soon as an evaluated cost is <= target."""
+    from scipy.optimize import minimize
+
+    tr = Trace()
+    best = [np.inf, np.asarray(theta0, dtype=np.float64).copy()]
+
+    class _Reached(Exception):
+        pass
+
+    def fun(th):
+        c, g = evaluate(th)
+        tr.costs.append(c)
+        tr.evals += 1
+        if c < best[0]:
+            best[0], best[1] = c, np.array(th, dtype=np.float64)
+        if target is not None and c <= target:
+            raise _Reached()
+        return c, g
+
+    t0 = time.perf_counter()
+    try:
+        res = minimize(fun, np.asarray(theta0, dtype=np.float64), jac=True, method="L-BFGS-B",
+                       callback=lambda xk: tr.thetas.append(np.array(xk)),
+                       options={"maxfun": max_evals, "maxiter": max_evals, "gtol": gtol, "ftol": ftol,
+                                "maxcor": memory})
+        tr.stop = str(res.message)
+    except _Reached:
+        tr.stop = "target reached"
+    tr.seconds = time.perf_counter() - t0
+    return best[1], tr
