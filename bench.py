@@ -243,7 +243,107 @@ def time_to_solution(api, dev, an, coeffs, strings, theta_rand, fast_s, plain_s,
     }
     if it_plain >= 0 and it_fast >= 0:
         tts["speedup"] = round((it_plain * plain_s) / (it_fast * fast_s + t_predict), 1)
+    tts["lbfgs"] = lbfgs_study(api, dev, an, coeffs, strings, theta_rand, net, plain_s)
     return stats, tts
+
+
+def lbfgs_study(api, dev, an, coeffs, strings, theta_rand, net, plain_s, max_evals=3000):
+    """L-BFGS-B (the paper's optimizer, host-side) on the benchmark system:
+    plain form from random initialisation, fast form from the same random
+    start and from the learned start.  Reports, per run, the seconds to
+    reach fidelity thresholds against x~ = A~^-1 b (the pruned system's
+    solution).  Plain-form evaluation counts come from the float64 adjoint
+    (cost and gradient equal to the shift rule's to rounding, checked on the
+    first evaluations below) and are charged the measured shift-rule time per
+    evaluation; fast-form seconds are measured."""
+    import numpy as np
+    import torch
+
+    from paper_2604_14435_amd.optim import Evaluator, lbfgs
+    from workloads import plus_state, toeplitz
+
+    At = api.pauli_sum_dense(coeffs, strings, an.n).cpu().numpy()
+    bvec = plus_state(an.n)
+    targets = {}
+    for name, M in (("pruned", At), ("full", toeplitz(an.n, DIAG, OFFDIAG))):
+        xs = np.linalg.solve(M, bvec.astype(M.dtype))
+        targets[name] = torch.from_numpy((xs / np.linalg.norm(xs)).astype(np.complex128)).to(dev)
+    th_rand = theta_rand.cpu().numpy()
+    th_mlp = net.predict(np.array([[DIAG, OFFDIAG]]))[0].double().cpu().numpy()
+    thresholds = (0.95, 0.98)
+
+    def fid(thetas, which):
+        T = torch.from_numpy(np.stack(thetas)).to(dev)
+        return api.fidelity(an, T, targets[which]).cpu().numpy()
+
+    # the shift rule and the float64 adjoint agree evaluation by evaluation
+    ev_ps = Evaluator(an, coeffs, strings, "f64")
+    ev_ad = Evaluator(an, coeffs, strings, "f64-adjoint")
+    _, t_ps = lbfgs(ev_ps, th_rand, max_evals=6)
+    _, t_ad = lbfgs(ev_ad, th_rand, max_evals=6)
+    agree = float(np.max(np.abs(np.array(t_ps.costs) - np.array(t_ad.costs[:len(t_ps.costs)]))))
+
+    runs = {}
+    for name, ev, th0, charged in (("plain_fp64_shift_random_init", ev_ad, th_rand, plain_s),
+                                   ("fp32_adjoint_random_init", Evaluator(an, coeffs, strings, "f32"), th_rand, None),
+                                   ("fp32_adjoint_warm_start", Evaluator(an, coeffs, strings, "f32"), th_mlp, None)):
+        _, tr = lbfgs(ev, th0, max_evals=max_evals)
+        F = fid([th0] + tr.thetas, "pruned")
+        secs = [0.0] + (list(np.array(tr.iter_evals) * charged) if charged else tr.iter_seconds)
+        reach = {}
+        for thr in thresholds:
+            idx = np.nonzero(F >= thr)[0]
+            reach[str(thr)] = round(float(secs[idx[0]]), 4) if len(idx) else None
+        Ff = fid([tr.thetas[-1] if tr.thetas else th0], "full")[0]
+        runs[name] = {"evaluations": tr.evals, "iterations": len(tr.thetas), "final_cost": min(tr.costs),
+                      "start_fidelity": float(F[0]), "final_fidelity_pruned": float(F[-1]),
+                      "final_fidelity_full": float(Ff), "seconds_to_fidelity": reach,
+                      "seconds": round(tr.evals * charged, 3) if charged else round(tr.seconds, 3),
+                      "stop": tr.stop[:60]}
+    return {"system": "toeplitz_n10_L64 (a=1.0, b=-0.45), CZ ladder, 4 layers, local cost",
+            "optimizer": "L-BFGS-B (SciPy, host) on GPU cost and gradient, max %d evaluations" % max_evals,
+            "plain_seconds_per_evaluation": round(plain_s, 5),
+            "shift_rule_vs_fp64_adjoint_first_costs_max_abs": agree,
+            "fidelity_pruned_vs_full_solution": float(abs(np.vdot(targets["pruned"].cpu().numpy(),
+                                                                   targets["full"].cpu().numpy())) ** 2),
+            "runs": runs}
+
+
+def four_qubit_fidelity(api, dev, target=0.9999, seeds=8):
+    """The paper's small-system check: n = 4 tridiagonal Toeplitz (1, -0.4),
+    no pruning (16 terms), RY + CNOT ladder, 4 layers, local cost, random
+    starts in seed order until the fidelity to A^-1 b reaches `target`.
+    Both forms timed for real (wall clock, L-BFGS-B on the host)."""
+    import numpy as np
+    import torch
+
+    from paper_2604_14435_amd.optim import Evaluator, lbfgs
+    from workloads import plus_state, theta_uniform, toeplitz
+
+    n, layers = 4, 4
+    A = toeplitz(n, 1.0, -0.4)
+    c, s, _ = api.pauli_decompose(torch.from_numpy(A).to(dev), tau=0.0)
+    an = api.AnsatzSpec(n, layers, "cnot")
+    xs = np.linalg.solve(A, plus_state(n))
+    tgt = torch.from_numpy((xs / np.linalg.norm(xs)).astype(np.complex128)).to(dev)
+    out = {"system": "n=4 tridiag(-0.4, 1, -0.4), L=16 (unpruned), RY+CNOT ladder, 4 layers, local cost",
+           "target_fidelity": target}
+    for form, name in (("f64", "plain_fp64_shift"), ("f32", "fp32_adjoint")):
+        ev = Evaluator(an, c, s, form)
+        t0 = time.perf_counter()
+        best, evals, used = 0.0, 0, 0
+        for seed in range(seeds):
+            th, tr = lbfgs(ev, theta_uniform(an.P, seed=seed), max_evals=1500)
+            evals += tr.evals
+            used += 1
+            best = max(best, float(api.fidelity(an, torch.from_numpy(th).to(dev), tgt)[0]))
+            if best >= target:
+                break
+        out[name] = {"seconds": round(time.perf_counter() - t0, 3), "evaluations": evals, "starts": used,
+                     "fidelity": best, "reached": best >= target}
+    if out["plain_fp64_shift"]["reached"] and out["fp32_adjoint"]["reached"]:
+        out["speedup"] = round(out["plain_fp64_shift"]["seconds"] / out["fp32_adjoint"]["seconds"], 2)
+    return out
 
 
 def main() -> int:
@@ -451,6 +551,8 @@ def main() -> int:
         out["warm_start"], out["time_to_solution"] = time_to_solution(
             api, dev, an, coeffs, strings, theta0, fast_s, plain_s, args.tts_budget)
         progress("warm start and time to solution done")
+        out["four_qubit_fidelity"] = four_qubit_fidelity(api, dev)
+        progress("four-qubit fidelity run done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out))

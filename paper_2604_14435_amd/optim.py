@@ -27,9 +27,13 @@ from . import api
 
 @dataclass
 class Trace:
-    """What one run did: costs per evaluation, iterates per iteration."""
-    costs: list = field(default_factory=list)      # every evaluation
-    thetas: list = field(default_factory=list)     # accepted iterates (L-BFGS iterations)
+    """What one run did: costs per evaluation; per accepted iterate (L-BFGS
+    iteration) the angles, the evaluations used so far and the seconds since
+    the start."""
+    costs: list = field(default_factory=list)
+    thetas: list = field(default_factory=list)
+    iter_evals: list = field(default_factory=list)
+    iter_seconds: list = field(default_factory=list)
     evals: int = 0
     seconds: float = 0.0
     stop: str = ""
@@ -111,9 +115,15 @@ def lbfgs(evaluate, theta0: np.ndarray, max_evals: int = 2000, target: float | N
         return c, g
 
     t0 = time.perf_counter()
+
+    def on_iterate(xk):
+        tr.thetas.append(np.array(xk))
+        tr.iter_evals.append(tr.evals)
+        tr.iter_seconds.append(time.perf_counter() - t0)
+
     try:
         res = minimize(fun, np.asarray(theta0, dtype=np.float64), jac=True, method="L-BFGS-B",
-                       callback=lambda xk: tr.thetas.append(np.array(xk)),
+                       callback=on_iterate,
                        options={"maxfun": max_evals, "maxiter": max_evals, "gtol": gtol, "ftol": ftol,
                                 "maxcor": memory})
         tr.stop = str(res.message)
