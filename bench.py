@@ -346,6 +346,70 @@ def four_qubit_fidelity(api, dev, target=0.9999, seeds=8):
     return out
 
 
+def heleshaw_run(api, dev, reps=3, iters=200):
+    """The Hele-Shaw-like pressure system (32 x 32 cells, seed 0, unit
+    spectral norm, normalised U(0,1) source), top-256 Pauli terms.
+    Throughput: one local-cost evaluation, 2(n+1)L^2 = 1,441,792 circuits
+    with the Householder U_b (general b: the LDS circuit kernel).
+    Convergence: L-BFGS-B for `iters` iterations on the complex64 adjoint
+    cost and gradient (RY + CNOT ladder, 6 layers), fidelity against the
+    dense float64 solves of the pruned and of the full system."""
+    import numpy as np
+    import torch
+
+    from paper_2604_14435_amd.optim import Evaluator, lbfgs
+    from workloads import heleshaw_like, theta_uniform
+
+    n = 10
+    A, bv = heleshaw_like(32, 0.5, seed=0)
+    Ad = torch.from_numpy(A).to(dev)
+    bt = torch.from_numpy(bv).to(dev)
+    coeffs, strings, ferr = api.pauli_decompose(Ad, top_L=256)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    coeffs, strings, ferr = api.pauli_decompose(Ad, top_L=256)
+    torch.cuda.synchronize()
+    dec_ms = (time.perf_counter() - t0) * 1e3
+    L = coeffs.shape[0]
+    an_t = api.AnsatzSpec(n, 4, "cz")
+    th = torch.from_numpy(theta_uniform(an_t.P, seed=0)).to(dev)
+    beta, other = api.vqls_terms(an_t, th, strings, "local", "f32", b_kind="vector", b=bt)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        api.vqls_terms(an_t, th, strings, "local", "f32", b_kind="vector", b=bt, out=(beta, other))
+    e1.record()
+    torch.cuda.synchronize()
+    eval_ms = e0.elapsed_time(e1) / reps
+    circuits = api.circuit_count(n, L, "local")
+    del beta, other
+
+    an = api.AnsatzSpec(n, 6, "cnot")
+    ev = Evaluator(an, coeffs, strings, "f32-adjoint", b_kind="vector", b=bt)
+    th0 = theta_uniform(an.P, seed=0)
+    c0, _ = ev(th0)
+    thf, tr = lbfgs(ev, th0, max_evals=4 * iters)
+    it = min(iters, len(tr.thetas))
+    thf = tr.thetas[it - 1] if it else th0
+    cf, _ = ev(thf)
+    At = api.pauli_sum_dense(coeffs, strings, n).real.cpu().numpy()
+    fids = {}
+    for name, M in (("vs_pruned_solution", At), ("vs_full_solution", A)):
+        xs = np.linalg.solve(M, bv)
+        tgt = torch.from_numpy((xs / np.linalg.norm(xs)).astype(np.complex128)).to(dev)
+        fids[name] = float(api.fidelity(an, torch.from_numpy(thf).to(dev), tgt)[0])
+    return {"workload": "heleshaw_n10_L256", "L": int(L), "frobenius_error": round(float(ferr), 5),
+            "decompose_ms": round(dec_ms, 3),
+            "terms_fp32_cz4": {"circuits": int(circuits), "ms": round(eval_ms, 3),
+                               "circuits_per_s": round(circuits / (eval_ms * 1e-3), 1),
+                               "kernel": "k_terms_generic<float> (Householder U_b, LDS state)"},
+            "lbfgs_fp32_adjoint_cnot6": {"iterations": it, "evaluations": tr.evals,
+                                         "seconds": round(tr.seconds, 3), "cost_start": c0, "cost_final": cf,
+                                         "fidelity": fids},
+            "condition_number": float(np.linalg.cond(A))}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -358,6 +422,7 @@ def main() -> int:
                     help="run one device copy of this many MiB first (calibrates HBM counters)")
     ap.add_argument("--no-fwht", action="store_true")
     ap.add_argument("--no-warmstart", action="store_true")
+    ap.add_argument("--no-heleshaw", action="store_true")
     ap.add_argument("--tts-budget", type=int, default=2000,
                     help="iteration budget of the time-to-solution comparison")
     args = ap.parse_args()
@@ -547,6 +612,9 @@ def main() -> int:
         "roofline_fwht": fwht,
     }
     progress("precision comparison done")
+    if not args.no_heleshaw:
+        out["heleshaw"] = heleshaw_run(api, dev)
+        progress("Hele-Shaw-like system done")
     if not args.no_warmstart:
         out["warm_start"], out["time_to_solution"] = time_to_solution(
             api, dev, an, coeffs, strings, theta0, fast_s, plain_s, args.tts_budget)

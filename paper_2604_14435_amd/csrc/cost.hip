@@ -13,16 +13,16 @@ constexpr int kCostThreads = 1024;
 //   Psi = sum_lm w_lm beta_lm;
 //   local:  E = sum_j sum_lm w_lm delta^j_lm, C = 1/2 - Re[E / (n Psi)] / 2;
 //   global: g = sum_l c_l gamma_l, G = |g|^2, C = 1 - G / Psi  (Eq. (1)).
-// Thread-strided partial sums, then the fixed-order block reduction, so the
-// result is bit-reproducible.
-__device__ __forceinline__ void acc_weighted(const dvq_c128* __restrict__ coeffs, int L, int64_t lm,
-                                             dvq_c128 t, double& ar, double& ai) {
-    const int l = (int)(lm / L), m = (int)(lm - (int64_t)l * L);
-    const dvq_c128 cl = coeffs[l], cm = coeffs[m];
-    const double wr = cl.re * cm.re + cl.im * cm.im, wi = cl.re * cm.im - cl.im * cm.re;
-    ar += wr * t.re - wi * t.im;
-    ai += wr * t.im + wi * t.re;
-}
+// The terms are rows of length L (beta rows, then the n delta rows of each
+// l); wavefront w takes the rows in blocks of kCostRows (block w, w + 16,
+// ...), the row index, and with it l and c_l, uniform over the wavefront,
+// and lane i the columns m = i, i + 64, ..., so c_m stays in registers.  A
+// block's loads are all issued before the first is used (the terms come
+// from HBM, and one workgroup needs many loads in flight).  Thread partial
+// sums in a fixed order, then the fixed-order block reduction: the result
+// is bit-reproducible.
+constexpr int kCostWaves = kCostThreads / 64;
+constexpr int kCostRows = 8;
 
 __global__ void __launch_bounds__(kCostThreads)
 k_cost(const dvq_c128* __restrict__ coeffs, int L, int n, int kind,
@@ -31,18 +31,44 @@ k_cost(const dvq_c128* __restrict__ coeffs, int L, int n, int kind,
     __shared__ double red[kCostThreads / 64];
     const int64_t row = blockIdx.x;
     const int64_t L2 = (int64_t)L * L;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // rows 0..L-1: beta; rows L..(n+1)L-1: delta (local only)
+    const int rows = kind == DVQ_COST_LOCAL ? (n + 1) * L : L;
     const dvq_c128* bt = beta + row * L2;
-    double pr = 0.0, pi = 0.0;
-#pragma unroll 4
-    for (int64_t i = threadIdx.x; i < L2; i += kCostThreads) acc_weighted(coeffs, L, i, bt[i], pr, pi);
+    const dvq_c128* dt = other + row * (int64_t)n * L2;
+    double pr = 0.0, pi = 0.0, nr = 0.0, ni = 0.0;
+    for (int m0 = 0; m0 < L; m0 += 64) {
+        const int m = m0 + lane;
+        const bool on = m < L;
+        const dvq_c128 cm = on ? coeffs[m] : dvq_c128{0.0, 0.0};
+        for (int r0 = wave * kCostRows; r0 < rows; r0 += kCostWaves * kCostRows) {
+            dvq_c128 t[kCostRows];
+#pragma unroll
+            for (int u = 0; u < kCostRows; ++u) {
+                const int r = r0 + u;
+                const dvq_c128* src = r < L ? bt + (int64_t)r * L : dt + (int64_t)(r - L) * L;
+                t[u] = (on && r < rows) ? src[m] : dvq_c128{0.0, 0.0};
+            }
+#pragma unroll
+            for (int u = 0; u < kCostRows; ++u) {
+                const int r = r0 + u;  // rows past the end loaded zeros
+                const dvq_c128 cl = coeffs[r % L];
+                const double wr = cl.re * cm.re + cl.im * cm.im, wi = cl.re * cm.im - cl.im * cm.re;
+                const double ar = wr * t[u].re - wi * t[u].im, ai = wr * t[u].im + wi * t[u].re;
+                if (r < L) {
+                    pr += ar;
+                    pi += ai;
+                } else {
+                    nr += ar;
+                    ni += ai;
+                }
+            }
+        }
+    }
     pr = block_sum(pr, red);
     pi = block_sum(pi, red);
-    double nr = 0.0, ni = 0.0, cost;
+    double cost;
     if (kind == DVQ_COST_LOCAL) {
-        const dvq_c128* dt = other + row * (int64_t)n * L2;
-        const int64_t tot = (int64_t)n * L2;
-#pragma unroll 4
-        for (int64_t i = threadIdx.x; i < tot; i += kCostThreads) acc_weighted(coeffs, L, i % L2, dt[i], nr, ni);
         nr = block_sum(nr, red);
         ni = block_sum(ni, red);
         cost = 0.5 - 0.5 * (nr * pr + ni * pi) / (n * (pr * pr + pi * pi));  // Re[E / (n Psi)]

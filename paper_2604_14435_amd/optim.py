@@ -9,9 +9,10 @@ libdvq.so:
     streams;
   * plain form ("f64"): cost and gradient from the parameter-shift rule,
     (2P + 1) evaluations of every circuit with complex128 states;
-  * adjoint form ("f64-adjoint"): cost and gradient from the complex128
-    adjoint sweep (same values as the plain form to rounding: the shift rule
-    is exact for RY gates).
+  * adjoint forms ("f64-adjoint", "f32-adjoint"): cost and gradient from
+    the adjoint sweep alone, complex128 or complex64 states (complex128: the
+    same values as the plain form to rounding, the shift rule being exact
+    for RY gates).
 Each evaluation ends with one device-to-host copy of (cost, gradient).
 """
 from __future__ import annotations
@@ -44,7 +45,7 @@ class Evaluator:
 
     def __init__(self, ansatz: api.AnsatzSpec, coeffs: torch.Tensor, strings: torch.Tensor, form: str,
                  kind: str = "local", b_kind: str = "plus", b=None):
-        if form not in ("f32", "f64", "f64-adjoint"):
+        if form not in ("f32", "f64", "f64-adjoint", "f32-adjoint"):
             raise ValueError(f"unknown form {form!r}")
         self.an, self.coeffs, self.strings, self.form = ansatz, coeffs, strings, form
         self.kind, self.b_kind, self.b = kind, b_kind, b
@@ -83,7 +84,7 @@ class Evaluator:
             api.vqls_grad_shift(self.an, self.theta[0], self.coeffs, self.strings, self.kind, "f64",
                                 b_kind=self.b_kind, b=self.b, workspace=self.ws, out=(self.C, self.g[0]))
         else:
-            api.vqls_grad_adjoint(self.an, self.theta, self.coeffs, self.strings, self.kind, "f64",
+            api.vqls_grad_adjoint(self.an, self.theta, self.coeffs, self.strings, self.kind, self.form[:3],
                                   b_kind=self.b_kind, b=self.b, out=(self.C, self.g))
         self.packed[0:1].copy_(self.C)
         self.packed[1:].copy_(self.g[0])
