@@ -10,7 +10,9 @@ One timed step = one VQLS iteration of the fast form:
   every circuit of the cost evaluation simulated with complex64 state
   vectors (float64 accumulation of the terms into the cost), the adjoint
   gradient (complex64 states, on a second stream beside the circuits: both
-  read the angles only) and the gradient-descent update after both.
+  read the angles only) and the gradient-descent update after the gradient;
+  the cost of each step is assembled on the second stream while the next
+  step's circuits run (two sets of term buffers).
 The plain form (complex128 states, gradient by the parameter-shift rule:
 (2P + 1) x 90,112 circuits per iteration) is timed beside it.
 
@@ -472,24 +474,36 @@ def main() -> int:
     ev = []
     main_s = torch.cuda.current_stream(dev)
     side_s = torch.cuda.Stream(device=dev)  # default priority
+    # two sets of term buffers: the cost of step k reads one while the
+    # circuits of step k + 1 write the other
+    bufs = [(beta, delta, C, parts),
+            (torch.empty_like(beta), torch.empty_like(delta), torch.empty_like(C), torch.empty_like(parts))]
+    step_no = [0]
 
     def fast_step(theta, record):
-        # The adjoint gradient and the circuit evaluation both read theta
-        # only: the gradient runs on a second stream beside the circuits,
-        # and the update waits for both.
+        # Step k: the adjoint gradient (side stream) and the circuits (main
+        # stream) both read theta_k; the update waits for the gradient only;
+        # the cost of step k runs on the side stream after the circuits, so
+        # it overlaps the circuits of step k + 1.
+        bb, dd, cc, pp = bufs[step_no[0] & 1]
+        step_no[0] += 1
         side_s.wait_stream(main_s)
         with torch.cuda.stream(side_s):
             api.vqls_grad_adjoint(an, theta, coeffs, strings, "local", "f32", out=(Ca, grad))
         if record:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(main_s)
-        api.vqls_terms(an, theta, strings, "local", "f32", out=(beta, delta))
+        api.vqls_terms(an, theta, strings, "local", "f32", out=(bb, dd))
+        done = torch.cuda.Event()
+        done.record(main_s)
         if record:
             e1.record(main_s)
             ev.append((e0, e1))
-        api.vqls_cost(coeffs, n, "local", beta, delta, out=(C, parts))
         main_s.wait_stream(side_s)
         api.gd_step(theta, grad, ETA)
+        side_s.wait_event(done)
+        with torch.cuda.stream(side_s):
+            api.vqls_cost(coeffs, n, "local", bb, dd, out=(cc, pp))
 
     theta = theta0.clone()
     for _ in range(args.warmup):

@@ -5,6 +5,8 @@
 // Circuit (b = |+>^n, so U_b Z_j U_b^dagger = H^n Z_j H^n = X_j):
 //   beta_lm:    H(anc); V(theta); C-A_m; C-A_l; [S^dagger(anc)]; H(anc); <Z_anc>
 //   delta^j_lm: H(anc); V(theta); C-A_m; C-X_j; C-A_l; [S^dagger]; H(anc); <Z_anc>
+// For a general real b, C-X_j becomes C-(U_b Z_j U_b^dagger) with the
+// Householder U_b (measure_suffix_bvec).
 //
 // Layout.  Lane bit 5 is the ancilla.  Two layouts alternate:
 //   LO: register bits = qubits 0..n-6, lane bits 0..4 = qubits n-5..n-1;
@@ -116,9 +118,12 @@ __device__ __forceinline__ T measure_suffix(const cplx<T>* S, SignedPerm sp, int
 // Both circuits (real, imaginary) of one term from one pass over the state:
 // the gathers and phases are shared, each circuit gets its own S^dagger,
 // H and <Z_anc>.
+// `src` is the offset of the half the controlled gates read (N: the
+// ancilla = 1 half; 0: the other half, which holds the same amplitudes,
+// when half 1 serves as scratch).
 template <typename T, int NQ>
 __device__ __forceinline__ void measure_suffix_pair(const cplx<T>* S, SignedPerm sp, int lane, T& zre,
-                                                    T& zim) {
+                                                    T& zim, int src = 1 << NQ) {
     constexpr int N = 1 << NQ;
     const T r2 = (T)0.70710678118654752440;
     T zr = 0, zi = 0;
@@ -126,7 +131,7 @@ __device__ __forceinline__ void measure_suffix_pair(const cplx<T>* S, SignedPerm
     for (int i = 0; i < N / 64; ++i) {
         const int k = lane + 64 * i;
         const cplx<T> a0 = S[pad_slot(k)];
-        const cplx<T> a1 = mul_ipow(S[pad_slot(N + (k ^ (int)sp.X))],
+        const cplx<T> a1 = mul_ipow(S[pad_slot(src + (k ^ (int)sp.X))],
                                     sp.pw + 2 * (int)(__popc((unsigned)k & sp.Z) & 1));
         // real-part circuit: H then <Z>
         T b0r = (a0.re + a1.re) * r2, b0i = (a0.im + a1.im) * r2;
@@ -144,8 +149,78 @@ __device__ __forceinline__ void measure_suffix_pair(const cplx<T>* S, SignedPerm
     zim = wave_sum(zi);
 }
 
+// Phase power of one Pauli string: (P v)[k] = i^p (-1)^{z.k} v[k ^ x] with
+// p = |x&z| + 2 (|x&z| mod 2) (P = i^{|x&z|} X^x Z^z).
+__device__ __forceinline__ int string_pow(const dvq_pauli ps) {
+    const int c = (int)__popc(ps.x & ps.z);
+    return c + 2 * (c & 1);
+}
+
+// delta^j_lm for a general real unit b (Householder U_b, U_b = U_b^dagger up
+// to a sign that cancels): U = A_l (H Z_j H) A_m with H = I - 2 w w^T / w^T w,
+// w = e_0 - s b.  On u = A_m psi,
+//   H Z_j H u = Z_j u + w (c1 + sigma c2),  sigma_k = (-1)^{k_j},
+//   c1 = -2 beta / om + 4 zeta alpha / om^2,  c2 = -2 alpha / om,
+//   alpha = w.u, beta = w.(Z_j u), zeta = w.(Z_j w), om = w.w,
+// so the circuit is one gather (u, into registers), five wave sums, one
+// write of H Z_j H u into the ancilla = 1 half of LDS and one gather of A_l
+// of it; then S^dagger / H / <Z_anc> for both parts as in
+// measure_suffix_pair.  `src` as there; the ancilla = 1 half is overwritten.
+template <typename T, int NQ>
+__device__ __forceinline__ void measure_suffix_bvec(cplx<T>* S, dvq_pauli pl, dvq_pauli pm, int j,
+                                                    const double* __restrict__ b, int lane, T& zre, T& zim,
+                                                    int src) {
+    constexpr int N = 1 << NQ, KPL = N / 64;
+    const double sg = (b[0] > 0.0) ? -1.0 : 1.0;
+    const int pwm = string_pow(pm);
+    cplx<T> u[KPL];
+    T ar = 0, ai = 0, br = 0, bi = 0, ze = 0, om = 0;
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+        const int k = lane + 64 * i;
+        u[i] = mul_ipow(S[pad_slot(src + (k ^ (int)pm.x))], pwm + 2 * (int)(__popc((unsigned)k & pm.z) & 1));
+        const T w = (T)((k == 0 ? 1.0 : 0.0) - sg * b[k]);
+        const T sw = ((k >> j) & 1) ? -w : w;
+        ar += w * u[i].re;
+        ai += w * u[i].im;
+        br += sw * u[i].re;
+        bi += sw * u[i].im;
+        ze += sw * w;
+        om += w * w;
+    }
+    ar = wave_sum(ar);
+    ai = wave_sum(ai);
+    br = wave_sum(br);
+    bi = wave_sum(bi);
+    ze = wave_sum(ze);
+    om = wave_sum(om);
+    const T io = (T)1 / om;
+    const T f = (T)4 * ze * io * io;
+    const T c1r = -(T)2 * br * io + f * ar, c1i = -(T)2 * bi * io + f * ai;
+    const T c2r = -(T)2 * ar * io, c2i = -(T)2 * ai * io;
+    __syncthreads();  // every lane has read its u
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+        const int k = lane + 64 * i;
+        const T w = (T)((k == 0 ? 1.0 : 0.0) - sg * b[k]);
+        const bool neg = (k >> j) & 1;
+        const T vr = neg ? -u[i].re : u[i].re, vi = neg ? -u[i].im : u[i].im;
+        const T er = neg ? c1r - c2r : c1r + c2r, ei = neg ? c1i - c2i : c1i + c2i;
+        S[pad_slot(N + k)] = {vr + w * er, vi + w * ei};
+    }
+    __syncthreads();
+    SignedPerm sp;
+    sp.X = pl.x;
+    sp.Z = pl.z;
+    sp.pw = string_pow(pl);
+    measure_suffix_pair<T, NQ>(S, sp, lane, zre, zim, N);
+}
+
 // Literal form: one wavefront simulates one circuit, every gate.
-template <typename T, int NQ, int ENT>
+// (No occupancy bound: at n = 10 in float32 the kernel takes 144 VGPRs,
+// three wavefronts per SIMD; bounding it to 128 for four spills to scratch
+// and measured 4 % slower.)
+template <typename T, int NQ, int ENT, bool BVEC>
 __global__ void __launch_bounds__(64) k_terms_fast(TermsArgs g) {
     constexpr int N = 1 << NQ;
     constexpr int NSLOT = 2 * N + (2 * N) / 32;
@@ -161,8 +236,15 @@ __global__ void __launch_bounds__(64) k_terms_fast(TermsArgs g) {
     const Term t = decode_term(gid - row * g.per_row, g.L, NQ, g.kind);
 
     simulate_prefix<T, NQ, ENT>(g.theta + row * P, g.layers, S, trig, lane);
-    const SignedPerm sp = suffix_perm(g.strings[t.l], g.strings[t.m], t.type, t.j);
-    const T z = measure_suffix<T, NQ>(S, sp, t.part, lane);
+    T z;
+    if (BVEC && t.type == kDelta) {
+        T zr, zi;
+        measure_suffix_bvec<T, NQ>(S, g.strings[t.l], g.strings[t.m], t.j, g.b, lane, zr, zi, N);
+        z = t.part ? zi : zr;
+    } else {
+        const SignedPerm sp = suffix_perm(g.strings[t.l], g.strings[t.m], t.type, t.j);
+        z = measure_suffix<T, NQ>(S, sp, t.part, lane);
+    }
     if (lane == 0) store_term(g, row, t, (double)z);
 }
 
@@ -170,7 +252,7 @@ __global__ void __launch_bounds__(64) k_terms_fast(TermsArgs g) {
 // once and then the distinct suffix of `chunk` consecutive circuits of the
 // same row (whole Re/Im pairs).  Same results as the literal form; the
 // ansatz work is paid once per chunk instead of once per circuit.
-template <typename T, int NQ, int ENT>
+template <typename T, int NQ, int ENT, bool BVEC>
 __global__ void __launch_bounds__(64) k_terms_shared(TermsArgs g, int64_t chunk, int64_t chunks_per_row) {
     constexpr int N = 1 << NQ;
     constexpr int NSLOT = 2 * N + (2 * N) / 32;
@@ -189,9 +271,14 @@ __global__ void __launch_bounds__(64) k_terms_shared(TermsArgs g, int64_t chunk,
     simulate_prefix<T, NQ, ENT>(g.theta + row * P, g.layers, S, trig, lane);
     for (int64_t c = c0; c < c1; c += 2) {
         const Term t = decode_term(c, g.L, NQ, g.kind);
-        const SignedPerm sp = suffix_perm(g.strings[t.l], g.strings[t.m], t.type, t.j);
         T zr, zi;
-        measure_suffix_pair<T, NQ>(S, sp, lane, zr, zi);
+        if (BVEC && t.type == kDelta) {
+            // reads half 0, uses half 1 as scratch
+            measure_suffix_bvec<T, NQ>(S, g.strings[t.l], g.strings[t.m], t.j, g.b, lane, zr, zi, 0);
+        } else {
+            const SignedPerm sp = suffix_perm(g.strings[t.l], g.strings[t.m], t.type, t.j);
+            measure_suffix_pair<T, NQ>(S, sp, lane, zr, zi, BVEC ? 0 : N);
+        }
         if (lane == 0) {
             store_term(g, row, t, (double)zr);
             Term ti = t;
@@ -207,19 +294,22 @@ static size_t fast_lds_bytes(int layers) {
     return (size_t)(2 * N + (2 * N) / 32) * sizeof(cplx<T>) + (size_t)2 * NQ * layers * sizeof(T);
 }
 
-template <typename T, int NQ, int ENT>
+template <typename T, int NQ, int ENT, bool BVEC>
 static dvq_status launch_fast_ent(const TermsArgs& g, hipStream_t s) {
     const size_t lds = fast_lds_bytes<T, NQ>(g.layers);
-    DVQ_TRY_HIP(allow_lds((const void*)k_terms_fast<T, NQ, ENT>, lds));
-    hipLaunchKernelGGL((k_terms_fast<T, NQ, ENT>), grid_for(g.total), dim3(64), lds, s, g);
+    DVQ_TRY_HIP(allow_lds((const void*)k_terms_fast<T, NQ, ENT, BVEC>, lds));
+    hipLaunchKernelGGL((k_terms_fast<T, NQ, ENT, BVEC>), grid_for(g.total), dim3(64), lds, s, g);
     DVQ_CHECK_LAUNCH("k_terms_fast");
     return DVQ_OK;
 }
 
 template <typename T, int NQ>
 static dvq_status launch_fast(const TermsArgs& g, hipStream_t s) {
-    return g.ent == DVQ_ENT_CZ_LADDER ? launch_fast_ent<T, NQ, DVQ_ENT_CZ_LADDER>(g, s)
-                                      : launch_fast_ent<T, NQ, DVQ_ENT_CNOT_LADDER>(g, s);
+    const bool cz = g.ent == DVQ_ENT_CZ_LADDER, bv = g.bkind == DVQ_B_VECTOR;
+    if (cz) return bv ? launch_fast_ent<T, NQ, DVQ_ENT_CZ_LADDER, true>(g, s)
+                      : launch_fast_ent<T, NQ, DVQ_ENT_CZ_LADDER, false>(g, s);
+    return bv ? launch_fast_ent<T, NQ, DVQ_ENT_CNOT_LADDER, true>(g, s)
+              : launch_fast_ent<T, NQ, DVQ_ENT_CNOT_LADDER, false>(g, s);
 }
 
 // Circuits per wavefront in the prefix-shared form: enough wavefronts to
@@ -233,25 +323,29 @@ static int64_t shared_chunk(int64_t per_row, int B) {
     return chunk;
 }
 
-template <typename T, int NQ, int ENT>
+template <typename T, int NQ, int ENT, bool BVEC>
 static dvq_status launch_shared_ent(const TermsArgs& g, hipStream_t s) {
     const size_t lds = fast_lds_bytes<T, NQ>(g.layers);
-    DVQ_TRY_HIP(allow_lds((const void*)k_terms_shared<T, NQ, ENT>, lds));
+    DVQ_TRY_HIP(allow_lds((const void*)k_terms_shared<T, NQ, ENT, BVEC>, lds));
     const int64_t chunk = shared_chunk(g.per_row, g.B);
     const int64_t cpr = (g.per_row + chunk - 1) / chunk;
-    hipLaunchKernelGGL((k_terms_shared<T, NQ, ENT>), grid_for(cpr * g.B), dim3(64), lds, s, g, chunk, cpr);
+    hipLaunchKernelGGL((k_terms_shared<T, NQ, ENT, BVEC>), grid_for(cpr * g.B), dim3(64), lds, s, g, chunk,
+                       cpr);
     DVQ_CHECK_LAUNCH("k_terms_shared");
     return DVQ_OK;
 }
 
 template <typename T, int NQ>
 static dvq_status launch_shared(const TermsArgs& g, hipStream_t s) {
-    return g.ent == DVQ_ENT_CZ_LADDER ? launch_shared_ent<T, NQ, DVQ_ENT_CZ_LADDER>(g, s)
-                                      : launch_shared_ent<T, NQ, DVQ_ENT_CNOT_LADDER>(g, s);
+    const bool cz = g.ent == DVQ_ENT_CZ_LADDER, bv = g.bkind == DVQ_B_VECTOR;
+    if (cz) return bv ? launch_shared_ent<T, NQ, DVQ_ENT_CZ_LADDER, true>(g, s)
+                      : launch_shared_ent<T, NQ, DVQ_ENT_CZ_LADDER, false>(g, s);
+    return bv ? launch_shared_ent<T, NQ, DVQ_ENT_CNOT_LADDER, true>(g, s)
+              : launch_shared_ent<T, NQ, DVQ_ENT_CNOT_LADDER, false>(g, s);
 }
 
 static bool fast_shape(const TermsArgs& g) {
-    return g.kind == DVQ_COST_LOCAL && g.bkind == DVQ_B_PLUS && g.n * g.layers <= 1024;
+    return g.kind == DVQ_COST_LOCAL && g.n * g.layers <= 1024 && (g.bkind == DVQ_B_PLUS || g.b != nullptr);
 }
 
 dvq_status launch_terms_fast(const TermsArgs& g, int precision, hipStream_t s) {

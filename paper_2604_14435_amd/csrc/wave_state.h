@@ -378,14 +378,21 @@ __device__ __forceinline__ void forward_layers(T* re, T* im, cplx<T>* S, const T
     }
 }
 
-// Rotation parameters of every gate: phi = theta/2 reduced to [-pi/2, pi/2].
+// Rotation parameters of every gate: phi = theta/2 reduced to [-pi/2, pi/2]
+// (in float64), then tan(phi/2) and sin(phi) = 2 t / (1 + t^2) in the state
+// precision.
 template <typename T>
 __device__ __forceinline__ void rotation_table(const double* __restrict__ theta, int P, T* trig, int lane) {
     for (int k = lane; k < P; k += 64) {
         double ph = 0.5 * theta[k];
         ph -= 3.14159265358979323846 * rint(ph * 0.31830988618379067154);
-        trig[2 * k] = (T)tan(0.5 * ph);
-        trig[2 * k + 1] = (T)sin(ph);
+        T t;
+        if constexpr (sizeof(T) == sizeof(float))
+            t = tanf(0.5f * (float)ph);
+        else
+            t = tan(0.5 * ph);
+        trig[2 * k] = t;
+        trig[2 * k + 1] = (T)2 * t / fmat(t, t, (T)1);
     }
     __syncthreads();
 }

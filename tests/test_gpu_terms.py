@@ -134,15 +134,17 @@ def test_bit_reproducible():
         assert torch.equal(b1, b2) and torch.equal(o1, o2)
 
 
+@pytest.mark.parametrize("bk", ["plus", "vector"])
 @pytest.mark.parametrize("ent", ["cz", "cnot"])
 @pytest.mark.parametrize("n,layers,precision", [(10, 1, "f32"), (10, 3, "f64"), (10, 5, "f32"),
                                                 (10, 6, "f64"), (11, 2, "f32"), (11, 3, "f32"),
                                                 (11, 4, "f32"), (10, 4, "f32")])
-def test_wavefront_kernel_shapes(n, layers, precision, ent):
-    """The register-resident kernel (n = 10, 11) with either ladder: even and
-    odd layer counts, a ragged L = 7 with x = 0 strings, odd Y counts and
-    every j; sampled terms against the oracle's circuits, and the full output
-    against the generic LDS kernel."""
+def test_wavefront_kernel_shapes(n, layers, precision, ent, bk):
+    """The register-resident kernel (n = 10, 11) with either ladder and
+    b = |+>^n or a general real b (Householder U_b): even and odd layer
+    counts, a ragged L = 7 with x = 0 strings, odd Y counts and every j;
+    sampled terms against the oracle's circuits, and the full output against
+    the generic LDS kernel."""
     rng = np.random.default_rng(n * 10 + layers)
     N = 1 << n
     strings = rng.integers(0, N, size=(7, 2)).astype(np.int32)
@@ -150,8 +152,10 @@ def test_wavefront_kernel_shapes(n, layers, precision, ent):
     strings[1, 0] = 0
     th = rng.uniform(0, 2 * math.pi, size=(2, n * layers))
     an = api.AnsatzSpec(n, layers, ent)
-    beta, delta = api.vqls_terms(an, _gpu(th), _gpu(strings), "local", precision)
-    gb, gd = api.vqls_terms(an, _gpu(th), _gpu(strings), "local", precision, exec_="generic")
+    bvec = random_unit_vector(1 << n, seed=n + layers) if bk == "vector" else None
+    bt = _gpu(bvec) if bk == "vector" else None
+    beta, delta = api.vqls_terms(an, _gpu(th), _gpu(strings), "local", precision, b_kind=bk, b=bt)
+    gb, gd = api.vqls_terms(an, _gpu(th), _gpu(strings), "local", precision, b_kind=bk, b=bt, exec_="generic")
     tol = TOL[precision]
     assert torch.max(torch.abs(beta - gb)).item() < 2 * tol
     assert torch.max(torch.abs(delta - gd)).item() < 2 * tol
@@ -162,12 +166,14 @@ def test_wavefront_kernel_shapes(n, layers, precision, ent):
             sl, sm = (int(strings[l, 0]), int(strings[l, 1])), (int(strings[m, 0]), int(strings[m, 1]))
             assert abs(beta[r, l, m] - qc.beta_term(th[r], n, layers, ent, sl, sm)) < tol
             j = int(rng.integers(0, n))
-            assert abs(delta[r, j, l, m] - qc.delta_term(th[r], n, layers, ent, sl, sm, j)) < tol
+            want = qc.delta_term(th[r], n, layers, ent, sl, sm, j, b_kind=bk, b=bvec)
+            assert abs(delta[r, j, l, m] - want) < tol
 
 
+@pytest.mark.parametrize("bk", ["plus", "vector"])
 @pytest.mark.parametrize("ent", ["cz", "cnot"])
 @pytest.mark.parametrize("n,layers,precision", [(10, 4, "f32"), (10, 3, "f64"), (11, 2, "f32")])
-def test_prefix_shared_mode(n, layers, precision, ent):
+def test_prefix_shared_mode(n, layers, precision, ent, bk):
     """Prefix-shared execution (ansatz once per wavefront, each circuit's own
     gates on a copy): B = 3 rows, ragged L = 9; sampled terms against the
     oracle's circuits and every term against the literal kernel."""
@@ -177,11 +183,15 @@ def test_prefix_shared_mode(n, layers, precision, ent):
     strings[2] = (0, 0)
     th = rng.uniform(0, 2 * math.pi, size=(3, n * layers))
     an = api.AnsatzSpec(n, layers, ent)
-    bs, ds = api.vqls_terms(an, _gpu(th), _gpu(strings), "local", precision, exec_="shared")
-    bl, dl = api.vqls_terms(an, _gpu(th), _gpu(strings), "local", precision, exec_="literal")
+    bvec = random_unit_vector(1 << n, seed=2 * n + layers) if bk == "vector" else None
+    bt = _gpu(bvec) if bk == "vector" else None
+    bs, ds = api.vqls_terms(an, _gpu(th), _gpu(strings), "local", precision, b_kind=bk, b=bt, exec_="shared")
+    bl, dl = api.vqls_terms(an, _gpu(th), _gpu(strings), "local", precision, b_kind=bk, b=bt, exec_="literal")
+    gb, gd = api.vqls_terms(an, _gpu(th), _gpu(strings), "local", precision, b_kind=bk, b=bt, exec_="generic")
     tol = TOL[precision]
     assert torch.max(torch.abs(bs - bl)).item() < 2 * tol
     assert torch.max(torch.abs(ds - dl)).item() < 2 * tol
+    assert torch.max(torch.abs(ds - gd)).item() < 2 * tol
     bs, ds = bs.cpu().numpy(), ds.cpu().numpy()
     for r in range(3):
         for _ in range(3):
@@ -189,4 +199,5 @@ def test_prefix_shared_mode(n, layers, precision, ent):
             sl, sm = (int(strings[l, 0]), int(strings[l, 1])), (int(strings[m, 0]), int(strings[m, 1]))
             assert abs(bs[r, l, m] - qc.beta_term(th[r], n, layers, ent, sl, sm)) < tol
             j = int(rng.integers(0, n))
-            assert abs(ds[r, j, l, m] - qc.delta_term(th[r], n, layers, ent, sl, sm, j)) < tol
+            want = qc.delta_term(th[r], n, layers, ent, sl, sm, j, b_kind=bk, b=bvec)
+            assert abs(ds[r, j, l, m] - want) < tol
