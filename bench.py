@@ -43,9 +43,9 @@ CSRC = os.path.join(ROOT, "paper_2604_14435_amd", "csrc")
 # Valid only for the kernel sources they were taken on: `sources_sha256` is
 # checked at run time and the figure is reported as null once they differ.
 MEASURED_TRAFFIC = {
-    "k_terms_fast<float,10,cz>": {
+    "k_terms_fast<float,10,cz,plus>": {
         "sources": ["circuits_fast.hip", "wave_state.h", "circuits.h", "common.h"],
-        "sources_sha256": "8df9cc9d91ffebf1", "fetch_kib": 252.1, "write_kib": 2816.0},
+        "sources_sha256": "cff488192784016b", "fetch_kib": 240.6, "write_kib": 2816.0},
     "k_fwht_fused<6,2> (n=12 dense)": {
         "sources": ["decompose.hip", "common.h"],
         "sources_sha256": "a4a7ec1ef26ff715", "fetch_kib": 66005.5, "write_kib": 262222.2},
@@ -352,7 +352,7 @@ def heleshaw_run(api, dev, reps=3, iters=200):
     """The Hele-Shaw-like pressure system (32 x 32 cells, seed 0, unit
     spectral norm, normalised U(0,1) source), top-256 Pauli terms.
     Throughput: one local-cost evaluation, 2(n+1)L^2 = 1,441,792 circuits
-    with the Householder U_b (general b: the LDS circuit kernel).
+    with the Householder U_b (general b, register-resident kernel).
     Convergence: L-BFGS-B for `iters` iterations on the complex64 adjoint
     cost and gradient (RY + CNOT ladder, 6 layers), fidelity against the
     dense float64 solves of the pruned and of the full system."""
@@ -405,11 +405,45 @@ def heleshaw_run(api, dev, reps=3, iters=200):
             "decompose_ms": round(dec_ms, 3),
             "terms_fp32_cz4": {"circuits": int(circuits), "ms": round(eval_ms, 3),
                                "circuits_per_s": round(circuits / (eval_ms * 1e-3), 1),
-                               "kernel": "k_terms_generic<float> (Householder U_b, LDS state)"},
+                               "kernel": "k_terms_fast<float,10,cz,vector> (Householder U_b in the suffix)"},
             "lbfgs_fp32_adjoint_cnot6": {"iterations": it, "evaluations": tr.evals,
                                          "seconds": round(tr.seconds, 3), "cost_start": c0, "cost_final": cf,
                                          "fidelity": fids},
             "condition_number": float(np.linalg.cond(A))}
+
+
+def pruning_sweep(api, dev):
+    """Accuracy of the pruned operator (Section III-B): n = 10,
+    tridiag(-1/3, 1, -1/3), the paper's tau list.  Decomposition, selection
+    and the relative Frobenius error on the GPU; the median relative
+    solution error of A~ x = b against A x = b over 64 normalised Gaussian
+    right-hand sides (seed 0) with dense float64 solves on the host.  The
+    paper's printed values (Section III-B) are listed beside them."""
+    import numpy as np
+    import torch
+
+    from workloads import gaussian_rhs, toeplitz
+
+    n = 10
+    A = toeplitz(n, 1.0, -1.0 / 3.0)
+    Ad = torch.from_numpy(A).to(dev)
+    rhs = gaussian_rhs(1 << n, 64, seed=0)
+    X = np.linalg.solve(A, rhs.T)
+    paper = {4: (21.28, 29.28), 64: (5.16, 7.15), 128: (3.53, 4.64)}
+    rows = []
+    for tau in (0.1, 0.05, 0.03, 0.02, 0.01, 0.005):
+        c, s, ferr = api.pauli_decompose(Ad, tau=tau)
+        L = int(c.shape[0])
+        At = api.pauli_sum_dense(c, s, n).real.cpu().numpy()
+        Xt = np.linalg.solve(At, rhs.T)
+        err = np.linalg.norm(Xt - X, axis=0) / np.linalg.norm(X, axis=0)
+        row = {"tau": tau, "L": L, "frobenius_error_percent": round(100 * ferr, 3),
+               "median_solution_error_percent": round(100 * float(np.median(err)), 3),
+               "circuits_per_evaluation": int(api.circuit_count(n, L, "local"))}
+        if L in paper:
+            row["paper"] = {"frobenius_error_percent": paper[L][0], "median_solution_error_percent": paper[L][1]}
+        rows.append(row)
+    return {"system": "n=10 tridiag(-1/3, 1, -1/3)", "rhs": "64 normalised Gaussian, seed 0", "rows": rows}
 
 
 def main() -> int:
@@ -592,8 +626,8 @@ def main() -> int:
     achieved = flops / (kern_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_ALU_PEAK,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_ALU_PEAK, 4),
-                "traffic": measured_traffic("k_terms_fast<float,10,cz>"),
-                "kernel": "k_terms_fast<float,10,cz>", "avg_kernel_ms": round(kern_ms, 4),
+                "traffic": measured_traffic("k_terms_fast<float,10,cz,plus>"),
+                "kernel": "k_terms_fast<float,10,cz,plus>", "avg_kernel_ms": round(kern_ms, 4),
                 "flops_per_launch": flops, "traffic_unit": "bytes per launch"}
 
     out = {
@@ -626,6 +660,7 @@ def main() -> int:
         "roofline_fwht": fwht,
     }
     progress("precision comparison done")
+    out["pruning_sweep"] = pruning_sweep(api, dev)
     if not args.no_heleshaw:
         out["heleshaw"] = heleshaw_run(api, dev)
         progress("Hele-Shaw-like system done")
