@@ -101,11 +101,12 @@ __device__ __forceinline__ void load_halves(T* re, T* im, const cplx<T>* S0, con
     constexpr int R = Lay<NQ, HI>::R;
     constexpr int N = 1 << NQ;
     const cplx<T>* src = (lane & 32) ? S1 : S0;
+    const LadderSign<NQ, HI> ls(lane);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int g = Lay<NQ, HI>::g(lane, r) & (N - 1);
         const cplx<T> v = src[pad_slot(g)];
-        const bool flip = p && ladder_flip<NQ>(g);
+        const bool flip = p && ls.flip(r);
         re[r] = flip ? -v.re : v.re;
         im[r] = flip ? -v.im : v.im;
     }
@@ -117,10 +118,11 @@ template <typename T, int NQ, bool HI>
 __device__ __forceinline__ void store_half0(const T* re, const T* im, cplx<T>* S0, int lane, int p) {
     constexpr int R = Lay<NQ, HI>::R;
     if (!(lane & 32)) {
+        const LadderSign<NQ, HI> ls(lane);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int g = Lay<NQ, HI>::g(lane, r);
-            const bool flip = p && ladder_flip<NQ>(g);
+            const bool flip = p && ls.flip(r);
             S0[pad_slot(g)] = flip ? cplx<T>{-re[r], -im[r]} : cplx<T>{re[r], im[r]};
         }
     }

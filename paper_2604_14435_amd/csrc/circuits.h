@@ -67,9 +67,12 @@ __device__ __forceinline__ void store_term(const TermsArgs& g, int64_t row, cons
     reinterpret_cast<double*>(dst)[t.part] = z;
 }
 
+// 2-D grid of at least `total` workgroups (x at most 65536), as few extra
+// (immediately exiting) workgroups as possible: gy rows of gx.
 inline dim3 grid_for(int64_t total) {
-    const int64_t gx = total < 65536 ? total : 65536;
-    return dim3((unsigned)gx, (unsigned)((total + gx - 1) / gx));
+    const int64_t gy = (total + 65535) / 65536;
+    const int64_t gx = (total + gy - 1) / gy;
+    return dim3((unsigned)gx, (unsigned)gy);
 }
 
 template <typename T>

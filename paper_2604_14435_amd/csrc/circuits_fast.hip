@@ -95,19 +95,49 @@ __device__ __forceinline__ SignedPerm suffix_perm(const dvq_pauli pl, const dvq_
     return sp;
 }
 
+// Basis state k = lane + 64 i of the lane's i-th amplitude: k ^ X and the
+// parity of k & Z split into a per-lane part and a part uniform over the
+// wavefront (i, X >> 6, Z >> 6), so the loop body needs one address add and
+// one phase add per amplitude.
+struct SuffixLane {
+    int base;  // pad_slot offset of (lane ^ (X & 63)) within a half
+    int pw;    // phase power from the lane bits
+    int xh, zh;
+};
+
+__device__ __forceinline__ SuffixLane suffix_lane(const SignedPerm& sp, int lane) {
+    SuffixLane sl;
+    const int b = lane ^ (int)(sp.X & 63u);
+    sl.base = b + (b >> 5);
+    sl.pw = sp.pw + 2 * (int)(__popc((unsigned)lane & (sp.Z & 63u)) & 1);
+    sl.xh = (int)(sp.X >> 6);
+    sl.zh = (int)(sp.Z >> 6);
+    return sl;
+}
+
+// pad_slot(src + ((lane ^ X) + 64 (i ^ xh))) = pad_slot(src) + base + 66 (i ^ xh)
+// (src a multiple of 64, lane ^ (X & 63) < 64).
+__device__ __forceinline__ int suffix_slot(const SuffixLane& sl, int src, int i) {
+    return src + (src >> 5) + sl.base + 66 * (i ^ sl.xh);
+}
+
+__device__ __forceinline__ int suffix_pow(const SuffixLane& sl, int i) {
+    return sl.pw + 2 * (int)(__popc((unsigned)(i & sl.zh)) & 1);
+}
+
 // <Z_anc> after applying U to the ancilla = 1 half, S^dagger (imag) and the
 // final H, summed over the lane's basis states and reduced over the wave.
 template <typename T, int NQ>
 __device__ __forceinline__ T measure_suffix(const cplx<T>* S, SignedPerm sp, int imag, int lane) {
     constexpr int N = 1 << NQ;
     const T r2 = (T)0.70710678118654752440;
+    const SuffixLane sl = suffix_lane(sp, lane);
     T z = 0;
 #pragma unroll 4
     for (int i = 0; i < N / 64; ++i) {
         const int k = lane + 64 * i;
         const cplx<T> a0 = S[pad_slot(k)];
-        const cplx<T> a1 = mul_ipow(S[pad_slot(N + (k ^ (int)sp.X))],
-                                    sp.pw + 2 * (int)(__popc((unsigned)k & sp.Z) & 1) + (imag ? 3 : 0));
+        const cplx<T> a1 = mul_ipow(S[suffix_slot(sl, N, i)], suffix_pow(sl, i) + (imag ? 3 : 0));
         const T b0r = (a0.re + a1.re) * r2, b0i = (a0.im + a1.im) * r2;
         const T b1r = (a0.re - a1.re) * r2, b1i = (a0.im - a1.im) * r2;
         z += (b0r * b0r + b0i * b0i) - (b1r * b1r + b1i * b1i);
@@ -126,13 +156,13 @@ __device__ __forceinline__ void measure_suffix_pair(const cplx<T>* S, SignedPerm
                                                     T& zim, int src = 1 << NQ) {
     constexpr int N = 1 << NQ;
     const T r2 = (T)0.70710678118654752440;
+    const SuffixLane sl = suffix_lane(sp, lane);
     T zr = 0, zi = 0;
 #pragma unroll 4
     for (int i = 0; i < N / 64; ++i) {
         const int k = lane + 64 * i;
         const cplx<T> a0 = S[pad_slot(k)];
-        const cplx<T> a1 = mul_ipow(S[pad_slot(src + (k ^ (int)sp.X))],
-                                    sp.pw + 2 * (int)(__popc((unsigned)k & sp.Z) & 1));
+        const cplx<T> a1 = mul_ipow(S[suffix_slot(sl, src, i)], suffix_pow(sl, i));
         // real-part circuit: H then <Z>
         T b0r = (a0.re + a1.re) * r2, b0i = (a0.im + a1.im) * r2;
         T b1r = (a0.re - a1.re) * r2, b1i = (a0.im - a1.im) * r2;

@@ -340,15 +340,35 @@ __device__ __forceinline__ bool ladder_flip(int g) {
     return __popc((unsigned)(g & (g >> 1) & ladder)) & 1;
 }
 
+// The CZ-ladder sign (-1)^{Q(g)} of amplitude (lane, r) of a layout.  With
+// g = glane | greg(r) on disjoint bits, Q(g) = Q(glane) + Q(greg) + the one
+// adjacent pair split between them (lane bit 4 and register bit 0 in HI,
+// register bit RB-1 and lane bit 0 in LO): two per-lane bits and
+// compile-time register parts, instead of a popcount per amplitude.
+template <int NQ, bool HI>
+struct LadderSign {
+    bool qa, la;
+    __device__ __forceinline__ explicit LadderSign(int lane) {
+        qa = ladder_flip<NQ>(Lay<NQ, HI>::glane(lane) & ((1 << NQ) - 1));
+        la = HI ? ((lane >> 4) & 1) : (lane & 1);
+    }
+    static constexpr bool qb(int r) {
+        return odd_bits(Lay<NQ, HI>::greg(r) & (Lay<NQ, HI>::greg(r) >> 1) & ((1 << (NQ - 1)) - 1));
+    }
+    static constexpr bool rb(int r) { return HI ? (r & 1) : ((r >> (Lay<NQ, HI>::RB - 1)) & 1); }
+    __device__ __forceinline__ bool flip(int r) const { return qa ^ qb(r) ^ (la && rb(r)); }
+};
+
 // Write the registers to LDS in natural order, applying S^p (the pending
 // CZ-ladder sign) on the way.
 template <typename T, int NQ, bool HI>
 __device__ __forceinline__ void store_state(const T* re, const T* im, cplx<T>* S, int lane, int p) {
     constexpr int R = Lay<NQ, HI>::R;
+    const LadderSign<NQ, HI> ls(lane);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int g = Lay<NQ, HI>::g(lane, r);
-        const bool flip = p && ladder_flip<NQ>(g);
+        const bool flip = p && ls.flip(r);
         S[pad_slot(g)] = flip ? cplx<T>{-re[r], -im[r]} : cplx<T>{re[r], im[r]};
     }
     __syncthreads();
