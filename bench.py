@@ -129,14 +129,14 @@ def warm_start_experiment(api, dev, n, layers, eta, budget, epochs, family_iters
     import numpy as np
     import torch
 
-    from paper_2604_14435_amd.warmstart import (MLPConfig, WarmStartMLP, decompose_family,
-                                                iterations_to, solve)
+    from paper_2604_14435_amd.warmstart import (MLPConfig, WarmStartMLP, decompose_batches, decompose_family,
+                                                iterations_to, solve, toeplitz_batches)
     from workloads import family_split, theta_uniform, toeplitz, toeplitz_family
 
     an = api.AnsatzSpec(n, layers, "cz")
     t0 = time.perf_counter()
     ab = toeplitz_family(4096, seed=0)
-    coeffs, strings, _ = decompose_family([toeplitz(n, a, b) for a, b in ab], 64, dev)
+    coeffs, strings, _ = decompose_batches(toeplitz_batches(ab, n, dev), 64)
     torch.cuda.synchronize()
     t_dec = time.perf_counter() - t0
     t0 = time.perf_counter()

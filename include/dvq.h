@@ -123,17 +123,42 @@ dvq_status dvq_pauli_decompose_dense(const double* A, int32_t n, dvq_c128* coeff
  *   coeffs   [capacity] output coefficients.
  *   strings  [capacity] output masks.
  *   capacity >= the number of kept terms, else DVQ_ECAPACITY (L_out_host is
- *            still written; coeffs/strings are not).  Threshold mode sorts
- *            at most 65536 kept terms (DVQ_ECAPACITY beyond).
+ *            still written; at most the first `capacity` entries of
+ *            coeffs/strings are written, their content is then
+ *            unspecified).  At most 65536 kept terms are sorted
+ *            (DVQ_ECAPACITY beyond).
  *   L_out_host     number of kept terms.
  *   frob_err_host  relative Frobenius error of the pruned sum,
  *                  sqrt(N * sum over dropped |c|^2) / ||A||_F (may be NULL).
- * Synchronises `stream` (host outputs).
+ * The selection runs on the device without host round trips; the call
+ * synchronises `stream` once at the end (host outputs).
  */
 dvq_status dvq_pauli_decompose(const double* A, int32_t n, double tau, int64_t top_L,
                                dvq_c128* coeffs, dvq_pauli* strings, int64_t capacity,
                                int64_t* L_out_host, double* frob_err_host,
                                void* workspace, size_t workspace_bytes, dvq_stream stream);
+
+/* Scratch bytes needed by dvq_pauli_decompose_batch for B matrices. */
+size_t dvq_decompose_batch_workspace_bytes(int32_t n, int32_t B);
+
+/*
+ * dvq_pauli_decompose in top-L mode for B matrices of one size (a family of
+ * systems, e.g. the training set of the warm start): Algorithm 1 Steps 1-2
+ * for each.  The matrices are processed one after another on `stream`, all
+ * enqueued before a single synchronisation.
+ *   A        [B][N][N] float64, row-major, device.
+ *   top_L    terms kept per matrix, 1 <= top_L <= min(4^n, 65536).
+ *   coeffs   [B][top_L], strings [B][top_L] (device): matrix b's terms,
+ *            ordered by the ranking key as in dvq_pauli_decompose.
+ *   frob_err_host [B] relative Frobenius error per matrix (host).
+ *   workspace >= dvq_decompose_batch_workspace_bytes(n, B) bytes, device.
+ * Errors: DVQ_EINVAL for bad arguments, DVQ_ECAPACITY for a short
+ * workspace, DVQ_EDEVICE if a device-side check fails (the message names
+ * the matrix).
+ */
+dvq_status dvq_pauli_decompose_batch(const double* A, int32_t n, int32_t B, int64_t top_L,
+                                     dvq_c128* coeffs, dvq_pauli* strings, double* frob_err_host,
+                                     void* workspace, size_t workspace_bytes, dvq_stream stream);
 
 /*
  * Dense operator of a term list: out[r][c] = sum_l c_l P_l[r][c] (Eq. (3)),

@@ -46,6 +46,9 @@ SIGNATURES = {
     "dvq_pauli_decompose_dense": (c_int32, [_V, c_int32, _V, _V, c_size_t, _V]),
     "dvq_pauli_decompose": (c_int32, [_V, c_int32, c_double, c_int64, _V, _V, c_int64,
                                       POINTER(c_int64), POINTER(c_double), _V, c_size_t, _V]),
+    "dvq_decompose_batch_workspace_bytes": (c_size_t, [c_int32, c_int32]),
+    "dvq_pauli_decompose_batch": (c_int32, [_V, c_int32, c_int32, c_int64, _V, _V, POINTER(c_double), _V,
+                                            c_size_t, _V]),
     "dvq_pauli_sum_dense": (c_int32, [_V, _V, c_int32, c_int32, _V, _V]),
     "dvq_circuit_count": (c_int64, [c_int32, c_int32, c_int32]),
     "dvq_vqls_terms": (c_int32, [_A, _V, c_int32, c_int32, _V, c_int32, c_int32, _V, c_int32,

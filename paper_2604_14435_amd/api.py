@@ -9,6 +9,7 @@ from __future__ import annotations
 import ctypes
 from dataclasses import dataclass
 
+import numpy as np
 import torch
 
 from . import _lib as L
@@ -98,6 +99,23 @@ def pauli_decompose(A: torch.Tensor, tau: float | None = None, top_L: int | None
            ctypes.byref(lout), ctypes.byref(ferr), _p(ws), ws.numel(), _stream(A))
     k = lout.value
     return coeffs[:k].clone(), strings[:k].clone(), ferr.value
+
+
+def pauli_decompose_batch(A: torch.Tensor, top_L: int, workspace: torch.Tensor | None = None):
+    """Top-L terms of each of B matrices A [B, N, N]: (coeffs complex128 [B, L],
+    strings int32 [B, L, 2], relative Frobenius errors float64 numpy [B])."""
+    A = _cuda(A, torch.float64, "A")
+    B, N = A.shape[0], A.shape[1]
+    n = N.bit_length() - 1
+    need = L.load().dvq_decompose_batch_workspace_bytes(n, B)
+    ws = workspace if workspace is not None and workspace.numel() >= need else \
+        torch.empty(need, dtype=torch.uint8, device=A.device)
+    coeffs = torch.empty((B, top_L), dtype=torch.complex128, device=A.device)
+    strings = torch.empty((B, top_L, 2), dtype=torch.int32, device=A.device)
+    ferr = (ctypes.c_double * B)()
+    L.call("dvq_pauli_decompose_batch", _p(A), n, B, int(top_L), _p(coeffs), _p(strings), ferr, _p(ws),
+           ws.numel(), _stream(A))
+    return coeffs, strings, np.array(ferr[:], dtype=np.float64)
 
 
 def pauli_sum_dense(coeffs: torch.Tensor, strings: torch.Tensor, n: int) -> torch.Tensor:

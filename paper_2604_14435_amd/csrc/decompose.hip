@@ -21,8 +21,10 @@
 // Selection ranks by the 96-bit key (bits of |r|, ~flat index): magnitude
 // descending, index ascending.  Threshold mode keeps |r| > tau; top-L mode
 // finds the L-th key with most-significant-digit-first radix selection
-// (8-bit digits, histogram per pass), then compacts the kept set and ranks
-// it exactly (each kept term counts the terms that precede it).
+// (8-bit digits, histogram per pass, the digit chosen on the device), then
+// compacts the kept set and ranks it exactly (each kept term counts the
+// terms that precede it).  The whole selection is enqueued without a host
+// round trip; one copy at the end returns the count and the error sums.
 #include "common.h"
 
 namespace dvq {
@@ -344,9 +346,59 @@ __global__ void k_fill_u32(uint32_t* p, int count, uint32_t v) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = v;
 }
 
+// State of the top-L radix selection, kept in device memory so that the
+// digit passes run without a host round trip: the key prefix chosen so far,
+// how many keys of the current bin are still needed, and flags.
+struct SelState {
+    uint64_t phi;   // magnitude bits of the prefix
+    int64_t need;   // keys still to take from the current prefix's bin
+    uint32_t plo;   // ~index bits of the prefix
+    uint32_t done;  // every key of the chosen bin is kept: later passes do nothing
+    uint32_t error; // a pass found fewer keys than needed
+    uint32_t pad;
+};
+
+__global__ void k_sel_init(SelState* __restrict__ st, uint32_t* __restrict__ hist, int64_t need) {
+    hist[threadIdx.x] = 0;
+    if (threadIdx.x == 0) *st = SelState{0ull, need, 0u, 0u, 0u, 0u};  // prefix 0, nothing done
+}
+
+// Choose digit d: the bin, scanned from the largest digit down, in which the
+// need-th key falls; then clear the histogram for the next pass.
+__global__ void __launch_bounds__(256) k_pick_digit(uint32_t* __restrict__ hist, int d, SelState* __restrict__ st) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = hist[threadIdx.x];
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    if (threadIdx.x != 0 || st->done) return;
+    int64_t above = 0;
+    int dig = -1;
+    for (int b = 255; b >= 0; --b) {
+        if (above + h[b] >= st->need) {
+            dig = b;
+            break;
+        }
+        above += h[b];
+    }
+    if (dig < 0) {
+        st->error = 1;
+        st->done = 1;
+        return;
+    }
+    st->need -= above;
+    if (d < 8)
+        st->phi |= (uint64_t)dig << (56 - 8 * d);
+    else
+        st->plo |= (uint32_t)dig << (24 - 8 * (d - 8));
+    if ((int64_t)h[dig] == st->need || d == 11) st->done = 1;
+}
+
 __global__ void __launch_bounds__(kDecThreads)
-k_digit_hist(const double* __restrict__ values, int64_t total, int d, uint64_t phi, uint32_t plo,
+k_digit_hist(const double* __restrict__ values, int64_t total, int d, const SelState* __restrict__ st,
              uint32_t* __restrict__ hist) {
+    if (st->done) return;
+    const uint64_t phi = st->phi;
+    const uint32_t plo = st->plo;
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
@@ -363,8 +415,10 @@ k_digit_hist(const double* __restrict__ values, int64_t total, int d, uint64_t p
 // Compact the kept terms (flat indices) into cand[0..count).
 //   mode 0: |r| > tau.   mode 1: key >= (thi, tlo).
 __global__ void __launch_bounds__(kDecThreads)
-k_compact(const double* __restrict__ values, int64_t total, int mode, double tau, uint64_t thi,
-          uint32_t tlo, uint32_t* __restrict__ counter, uint32_t* __restrict__ cand, int cap) {
+k_compact(const double* __restrict__ values, int64_t total, int mode, double tau, const SelState* __restrict__ st,
+          uint32_t* __restrict__ counter, uint32_t* __restrict__ cand, int cap) {
+    const uint64_t thi = mode == 1 ? st->phi : 0ull;
+    const uint32_t tlo = mode == 1 ? st->plo : 0u;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double r = values[i];
@@ -383,30 +437,18 @@ k_compact(const double* __restrict__ values, int64_t total, int mode, double tau
     }
 }
 
-// Count |r| > tau (mode 0) per block into partial counts.
+// Exact rank of each kept term; writes the outputs in ranking order.  The
+// count is the device-side compaction count (at most `limit` candidates were
+// stored); ranks at or beyond `cap` (the caller's capacity) are not written,
+// the host reports that case after the final synchronisation.
 __global__ void __launch_bounds__(kDecThreads)
-k_count_tau(const double* __restrict__ values, int64_t total, double tau, uint32_t* __restrict__ counter) {
-    uint32_t c = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x)
-        c += fabs(values[i]) > tau ? 1u : 0u;
-    __shared__ uint32_t red[kDecThreads / 64];
-    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t s = 0;
-        for (int w = 0; w < kDecThreads / 64; ++w) s += red[w];
-        if (s) atomicAdd(counter, s);
-    }
-}
-
-// Exact rank of each kept term; writes the outputs in ranking order.
-__global__ void __launch_bounds__(kDecThreads)
-k_rank_write(const double* __restrict__ values, const uint32_t* __restrict__ cand, int count, int n,
-             dvq_c128* __restrict__ coeffs, dvq_pauli* __restrict__ strings) {
+k_rank_write(const double* __restrict__ values, const uint32_t* __restrict__ cand,
+             const uint32_t* __restrict__ counter, int limit, int64_t cap, int n, dvq_c128* __restrict__ coeffs,
+             dvq_pauli* __restrict__ strings) {
     __shared__ uint64_t th[kDecThreads];
     __shared__ uint32_t ti[kDecThreads];
+    const int count = (int)(*counter < (uint32_t)limit ? *counter : (uint32_t)limit);
+    if ((int)(blockIdx.x * blockDim.x) >= count) return;  // whole block idle
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t mh = 0;
     uint32_t mi = 0;
@@ -427,7 +469,7 @@ k_rank_write(const double* __restrict__ values, const uint32_t* __restrict__ can
             for (int t = 0; t < lim; ++t) rank += (th[t] > mh) || (th[t] == mh && ti[t] < mi);
         __syncthreads();
     }
-    if (i < count) {
+    if (i < count && rank < cap) {
         const uint32_t x = mi >> n, z = mi & ((1u << n) - 1);
         coeffs[rank] = phase_mul(values[mi], x, z);
         strings[rank] = {x, z};
@@ -437,9 +479,11 @@ k_rank_write(const double* __restrict__ values, const uint32_t* __restrict__ can
 // Per-block partial sums (fixed grid, fixed order) of r^2 over the dropped
 // terms (mode 0: |r| <= tau; mode 1: key < threshold) and of A^2.
 __global__ void __launch_bounds__(kDecThreads)
-k_partial_sq(const double* __restrict__ v, int64_t total, int mode, double tau, uint64_t thi,
-             uint32_t tlo, double* __restrict__ partials) {
+k_partial_sq(const double* __restrict__ v, int64_t total, int mode, double tau, const SelState* __restrict__ st,
+             double* __restrict__ partials) {
     __shared__ double red[kDecThreads / 64];
+    const uint64_t thi = mode == 1 ? st->phi : 0ull;
+    const uint32_t tlo = mode == 1 ? st->plo : 0u;
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -501,6 +545,7 @@ struct DecWs {
     uint32_t* cand;     // kSortMax
     double* partials;   // kPartials
     double* sums;       // 2
+    SelState* sel;      // 1
 };
 
 static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
@@ -522,6 +567,7 @@ static size_t dec_ws_layout(int n, DecWs* ws, void* base) {
     w.cand = reinterpret_cast<uint32_t*>(take(kSortMax * sizeof(uint32_t)));
     w.partials = reinterpret_cast<double*>(take(kPartials * sizeof(double)));
     w.sums = reinterpret_cast<double*>(take(2 * sizeof(double)));
+    w.sel = reinterpret_cast<SelState*>(take(sizeof(SelState)));
     if (ws) *ws = w;
     return off;
 }
@@ -573,6 +619,86 @@ dvq_status dvq_pauli_decompose_dense(const double* A, int32_t n, dvq_c128* coeff
     return run_fwht(A, n, w.T, coeffs_all, nullptr, stream_of(stream));
 }
 
+}  // extern "C"
+
+namespace dvq {
+
+// Enqueue the whole decomposition + selection of one matrix on `s` (no host
+// round trip); the results that the host checks go to sel, counter, sums.
+static dvq_status enqueue_decompose(const double* A, int n, double tau, int64_t top_L, dvq_c128* coeffs,
+                                    dvq_pauli* strings, int64_t capacity, bool frob, const DecWs& w,
+                                    SelState* sel, uint32_t* counter, double* sums, hipStream_t s) {
+    const int64_t total = int64_t(1) << (2 * n);
+    const int blocks = stream_blocks(total);
+    dvq_status st = run_fwht(A, n, w.T, nullptr, w.values, s);
+    if (st != DVQ_OK) return st;
+    const int mode = top_L <= 0 ? 0 : 1;
+    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, sel, w.hist, mode ? top_L : 0);
+    DVQ_CHECK_LAUNCH("k_sel_init");
+    if (mode == 1) {
+        // most-significant-digit-first radix selection of the top_L-th key
+        for (int d = 0; d < 12; ++d) {
+            hipLaunchKernelGGL(k_digit_hist, dim3(blocks), dim3(kDecThreads), 0, s, w.values, total, d, sel,
+                               w.hist);
+            DVQ_CHECK_LAUNCH("k_digit_hist");
+            hipLaunchKernelGGL(k_pick_digit, dim3(1), dim3(256), 0, s, w.hist, d, sel);
+            DVQ_CHECK_LAUNCH("k_pick_digit");
+        }
+    }
+    if ((st = fill_u32(counter, 1, 0u, s)) != DVQ_OK) return st;
+    hipLaunchKernelGGL(k_compact, dim3(blocks), dim3(kDecThreads), 0, s, w.values, total, mode, tau, sel, counter,
+                       w.cand, kSortMax);
+    DVQ_CHECK_LAUNCH("k_compact");
+    hipLaunchKernelGGL(k_rank_write, dim3(kSortMax / kDecThreads), dim3(kDecThreads), 0, s, w.values, w.cand,
+                       counter, kSortMax, capacity, n, coeffs, strings);
+    DVQ_CHECK_LAUNCH("k_rank_write");
+    if (frob) {
+        const int pb = kPartials;
+        hipLaunchKernelGGL(k_partial_sq, dim3(pb), dim3(kDecThreads), 0, s, w.values, total, mode, tau, sel,
+                           w.partials);
+        DVQ_CHECK_LAUNCH("k_partial_sq");
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kDecThreads), 0, s, w.partials, pb, sums);
+        DVQ_CHECK_LAUNCH("k_sum_partials");
+        hipLaunchKernelGGL(k_partial_sq, dim3(pb), dim3(kDecThreads), 0, s, A, total, 2, 0.0, sel, w.partials);
+        DVQ_CHECK_LAUNCH("k_partial_sq");
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kDecThreads), 0, s, w.partials, pb, sums + 1);
+        DVQ_CHECK_LAUNCH("k_sum_partials");
+    }
+    return DVQ_OK;
+}
+
+// The host checks of one decomposition after the final synchronisation.
+static dvq_status check_decompose(int n, int64_t top_L, int64_t capacity, const SelState& sel, uint32_t counter,
+                                  const double* sums, int64_t* L_out, double* frob_err, int index) {
+    if (sel.error) return fail(DVQ_EDEVICE, "matrix %d: radix selection lost elements", index);
+    const int64_t kept = top_L > 0 ? top_L : (int64_t)counter;
+    if (L_out) *L_out = kept;
+    if (kept > capacity)
+        return fail(DVQ_ECAPACITY, "%lld kept terms > capacity %lld", (long long)kept, (long long)capacity);
+    if (kept > kSortMax)
+        return fail(DVQ_ECAPACITY, "%lld kept terms > %d (sort limit)", (long long)kept, kSortMax);
+    if ((int64_t)counter != kept)
+        return fail(DVQ_EDEVICE, "matrix %d: compaction kept %u terms, expected %lld", index, counter,
+                    (long long)kept);
+    if (frob_err) {
+        const double N = (double)(int64_t(1) << n);
+        *frob_err = sums[1] > 0.0 ? sqrt(N * sums[0]) / sqrt(sums[1]) : 0.0;
+    }
+    return DVQ_OK;
+}
+
+// Per-matrix result slot of the batched form, after the shared workspace.
+struct DecSlot {
+    SelState sel;
+    uint32_t counter;
+    uint32_t pad;
+    double sums[2];
+};
+
+}  // namespace dvq
+
+extern "C" {
+
 dvq_status dvq_pauli_decompose(const double* A, int32_t n, double tau, int64_t top_L,
                                dvq_c128* coeffs, dvq_pauli* strings, int64_t capacity,
                                int64_t* L_out_host, double* frob_err_host, void* workspace,
@@ -589,100 +715,58 @@ dvq_status dvq_pauli_decompose(const double* A, int32_t n, double tau, int64_t t
     hipStream_t s = stream_of(stream);
     DecWs w;
     dec_ws_layout(n, &w, workspace);
-    dvq_status st = run_fwht(A, n, w.T, nullptr, w.values, s);
+    dvq_status st = enqueue_decompose(A, n, tau, top_L, coeffs, strings, capacity, frob_err_host != nullptr, w,
+                                      w.sel, w.counter, w.sums, s);
     if (st != DVQ_OK) return st;
-    const int blocks = stream_blocks(total);
-
-    int mode;
-    uint64_t thi = 0;
-    uint32_t tlo = 0;
-    int64_t kept;
-    if (top_L <= 0) {
-        mode = 0;
-        if ((st = fill_u32(w.counter, 1, 0u, s)) != DVQ_OK) return st;
-        hipLaunchKernelGGL(k_count_tau, dim3(blocks), dim3(kDecThreads), 0, s, w.values, total, tau,
-                           w.counter);
-        DVQ_CHECK_LAUNCH("k_count_tau");
-        uint32_t cnt = 0;
-        DVQ_TRY_HIP(hipMemcpyAsync(&cnt, w.counter, sizeof(cnt), hipMemcpyDeviceToHost, s));
-        DVQ_TRY_HIP(hipStreamSynchronize(s));
-        kept = cnt;
-    } else {
-        // most-significant-digit-first radix selection of the top_L-th key
-        mode = 1;
-        uint64_t phi = 0;
-        uint32_t plo = 0;
-        int64_t need_sel = top_L;
-        for (int d = 0; d < 12; ++d) {
-            if ((st = fill_u32(w.hist, 256, 0u, s)) != DVQ_OK) return st;
-            hipLaunchKernelGGL(k_digit_hist, dim3(blocks), dim3(kDecThreads), 0, s, w.values, total, d,
-                               phi, plo, w.hist);
-            DVQ_CHECK_LAUNCH("k_digit_hist");
-            uint32_t h[256];
-            DVQ_TRY_HIP(hipMemcpyAsync(h, w.hist, sizeof(h), hipMemcpyDeviceToHost, s));
-            DVQ_TRY_HIP(hipStreamSynchronize(s));
-            int64_t above = 0;
-            int dig = -1;
-            for (int b = 255; b >= 0; --b) {
-                if (above + h[b] >= need_sel) {
-                    dig = b;
-                    break;
-                }
-                above += h[b];
-            }
-            if (dig < 0) return fail(DVQ_EDEVICE, "radix selection lost elements at digit %d", d);
-            need_sel -= above;
-            if (d < 8)
-                phi |= (uint64_t)dig << (56 - 8 * d);
-            else
-                plo |= (uint32_t)dig << (24 - 8 * (d - 8));
-            if (h[dig] == need_sel) break;  // every key in this bin is kept
-        }
-        thi = phi;
-        tlo = plo;
-        kept = top_L;
-    }
-    *L_out_host = kept;
-    if (kept > capacity)
-        return fail(DVQ_ECAPACITY, "%lld kept terms > capacity %lld", (long long)kept, (long long)capacity);
-    if (kept > kSortMax)
-        return fail(DVQ_ECAPACITY, "%lld kept terms > %d (sort limit)", (long long)kept, kSortMax);
-    if ((st = fill_u32(w.counter, 1, 0u, s)) != DVQ_OK) return st;
-    hipLaunchKernelGGL(k_compact, dim3(blocks), dim3(kDecThreads), 0, s, w.values, total, mode, tau, thi,
-                       tlo, w.counter, w.cand, kSortMax);
-    DVQ_CHECK_LAUNCH("k_compact");
-    // The ranking kernel reads cand[0 .. kept): confirm every slot was written.
-    uint32_t compacted = 0;
-    DVQ_TRY_HIP(hipMemcpyAsync(&compacted, w.counter, sizeof(compacted), hipMemcpyDeviceToHost, s));
+    uint32_t counter = 0;
+    SelState sel;
+    double sums[2] = {0.0, 0.0};
+    DVQ_TRY_HIP(hipMemcpyAsync(&counter, w.counter, sizeof(counter), hipMemcpyDeviceToHost, s));
+    DVQ_TRY_HIP(hipMemcpyAsync(&sel, w.sel, sizeof(sel), hipMemcpyDeviceToHost, s));
+    if (frob_err_host) DVQ_TRY_HIP(hipMemcpyAsync(sums, w.sums, sizeof(sums), hipMemcpyDeviceToHost, s));
     DVQ_TRY_HIP(hipStreamSynchronize(s));
-    if ((int64_t)compacted != kept)
-        return fail(DVQ_EDEVICE, "compaction kept %u terms, expected %lld", compacted, (long long)kept);
-    if (kept > 0) {
-        hipLaunchKernelGGL(k_rank_write, dim3((unsigned)((kept + kDecThreads - 1) / kDecThreads)),
-                           dim3(kDecThreads), 0, s, w.values, w.cand, (int)kept, n, coeffs, strings);
-        DVQ_CHECK_LAUNCH("k_rank_write");
+    return check_decompose(n, top_L, capacity, sel, counter, sums, L_out_host, frob_err_host, 0);
+}
+
+size_t dvq_decompose_batch_workspace_bytes(int32_t n, int32_t B) {
+    if (n < 1 || n > 12 || B < 1) return 0;
+    return dec_ws_layout(n, nullptr, nullptr) + (size_t)B * sizeof(DecSlot);
+}
+
+dvq_status dvq_pauli_decompose_batch(const double* A, int32_t n, int32_t B, int64_t top_L, dvq_c128* coeffs,
+                                     dvq_pauli* strings, double* frob_err_host, void* workspace,
+                                     size_t workspace_bytes, dvq_stream stream) {
+    DVQ_REQUIRE(n >= 1 && n <= 12, "n=%d outside 1..12", n);
+    DVQ_REQUIRE(B >= 1, "B=%d < 1", B);
+    DVQ_REQUIRE(A && coeffs && strings && frob_err_host, "null pointer");
+    const int64_t total = int64_t(1) << (2 * n);
+    DVQ_REQUIRE(top_L >= 1 && top_L <= total && top_L <= kSortMax, "top_L=%lld outside 1..min(4^n, %d)",
+                (long long)top_L, kSortMax);
+    const size_t need = dvq_decompose_batch_workspace_bytes(n, B);
+    if (workspace == nullptr || workspace_bytes < need)
+        return fail(DVQ_ECAPACITY, "decompose workspace %zu B < %zu B", workspace_bytes, need);
+    hipStream_t s = stream_of(stream);
+    DecWs w;
+    const size_t shared = dec_ws_layout(n, &w, workspace);
+    DecSlot* slots = reinterpret_cast<DecSlot*>(static_cast<char*>(workspace) + shared);
+    const int64_t N2 = total;
+    for (int b = 0; b < B; ++b) {
+        dvq_status st = enqueue_decompose(A + (int64_t)b * N2, n, 0.0, top_L, coeffs + (int64_t)b * top_L,
+                                          strings + (int64_t)b * top_L, top_L, true, w, &slots[b].sel,
+                                          &slots[b].counter, slots[b].sums, s);
+        if (st != DVQ_OK) return st;
     }
-    if (frob_err_host) {
-        const int pb = kPartials;
-        hipLaunchKernelGGL(k_partial_sq, dim3(pb), dim3(kDecThreads), 0, s, w.values, total, mode, tau, thi,
-                           tlo, w.partials);
-        DVQ_CHECK_LAUNCH("k_partial_sq");
-        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kDecThreads), 0, s, w.partials, pb, w.sums);
-        DVQ_CHECK_LAUNCH("k_sum_partials");
-        hipLaunchKernelGGL(k_partial_sq, dim3(pb), dim3(kDecThreads), 0, s, A, total, 2, 0.0, 0ull, 0u,
-                           w.partials);
-        DVQ_CHECK_LAUNCH("k_partial_sq");
-        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kDecThreads), 0, s, w.partials, pb, w.sums + 1);
-        DVQ_CHECK_LAUNCH("k_sum_partials");
-        double sums[2];
-        DVQ_TRY_HIP(hipMemcpyAsync(sums, w.sums, sizeof(sums), hipMemcpyDeviceToHost, s));
-        DVQ_TRY_HIP(hipStreamSynchronize(s));
-        const double N = (double)(int64_t(1) << n);
-        *frob_err_host = sums[1] > 0.0 ? sqrt(N * sums[0]) / sqrt(sums[1]) : 0.0;
-    } else {
-        DVQ_TRY_HIP(hipStreamSynchronize(s));
-    }
-    return DVQ_OK;
+    DecSlot* host = static_cast<DecSlot*>(malloc(sizeof(DecSlot) * (size_t)B));
+    if (!host) return fail(DVQ_EDEVICE, "host allocation of %d result slots failed", B);
+    hipError_t e = hipMemcpyAsync(host, slots, sizeof(DecSlot) * (size_t)B, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dvq_status st = DVQ_OK;
+    if (e != hipSuccess) st = fail(DVQ_EDEVICE, "batched decomposition: %s", hipGetErrorString(e));
+    for (int b = 0; b < B && st == DVQ_OK; ++b)
+        st = check_decompose(n, top_L, top_L, host[b].sel, host[b].counter, host[b].sums, nullptr,
+                             &frob_err_host[b], b);
+    free(host);
+    return st;
 }
 
 }  // extern "C"

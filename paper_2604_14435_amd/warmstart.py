@@ -21,19 +21,58 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
+from . import _lib as L
 from . import api
 
 
-def decompose_family(matrices, top_L: int, device) -> tuple[torch.Tensor, torch.Tensor, np.ndarray]:
-    """Top-L terms of each matrix: coeffs [S, L] complex128, strings [S, L, 2] int32,
-    relative Frobenius errors [S]."""
+def decompose_batches(batches, top_L: int) -> tuple[torch.Tensor, torch.Tensor, np.ndarray]:
+    """Top-L terms of every matrix of an iterable of device batches [b, N, N]
+    (one batched call per batch): coeffs [S, L] complex128, strings
+    [S, L, 2] int32, relative Frobenius errors [S]."""
     cs, ss, fe = [], [], []
-    for A in matrices:
-        c, s, f = api.pauli_decompose(torch.as_tensor(A, device=device), top_L=top_L)
+    ws = None
+    for A in batches:
+        n = A.shape[1].bit_length() - 1
+        need = L.load().dvq_decompose_batch_workspace_bytes(n, A.shape[0])
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(need, dtype=torch.uint8, device=A.device)
+        c, s, f = api.pauli_decompose_batch(A, top_L, workspace=ws)
         cs.append(c)
         ss.append(s)
         fe.append(f)
-    return torch.stack(cs), torch.stack(ss), np.array(fe)
+    return torch.cat(cs), torch.cat(ss), np.concatenate(fe)
+
+
+def decompose_family(matrices, top_L: int, device, chunk: int = 256
+                     ) -> tuple[torch.Tensor, torch.Tensor, np.ndarray]:
+    """Top-L terms of each host matrix of an iterable, `chunk` per batched call."""
+    import itertools
+
+    it = iter(matrices)
+
+    def batches():
+        while True:
+            part = list(itertools.islice(it, chunk))
+            if not part:
+                return
+            yield torch.from_numpy(np.stack(part)).to(device)
+
+    return decompose_batches(batches(), top_L)
+
+
+def toeplitz_batches(ab: np.ndarray, n: int, device, chunk: int = 256):
+    """The tridiagonal Toeplitz matrices of the (a, b) pairs (diagonal a,
+    both off-diagonals b: the same matrices as workloads.toeplitz(n, a, b)),
+    built in device memory `chunk` at a time; yields [b, N, N] float64."""
+    N = 1 << n
+    idx = torch.arange(N, device=device)
+    for s0 in range(0, len(ab), chunk):
+        part = torch.as_tensor(np.ascontiguousarray(ab[s0:s0 + chunk]), dtype=torch.float64, device=device)
+        A = torch.zeros((part.shape[0], N, N), dtype=torch.float64, device=device)
+        A[:, idx, idx] = part[:, 0:1]
+        A[:, idx[:-1], idx[:-1] + 1] = part[:, 1:2]
+        A[:, idx[:-1] + 1, idx[:-1]] = part[:, 1:2]
+        yield A
 
 
 def solve(ansatz: api.AnsatzSpec, coeffs, strings, theta0: torch.Tensor, iters: int, lr: float,

@@ -82,6 +82,22 @@ def test_decompose_rejects_bad_input():
     assert lib.dvq_decompose_workspace_bytes(13) == 0
 
 
+def test_decompose_batch_rejects_bad_input():
+    lib = L.load()
+    d = ctypes.c_void_p(16)
+    f = (ctypes.c_double * 4)()
+    big = 1 << 40
+    assert lib.dvq_pauli_decompose_batch(d, 4, 0, 8, d, d, f, d, big, None) == L.DVQ_EINVAL  # B < 1
+    assert lib.dvq_pauli_decompose_batch(d, 4, 4, 0, d, d, f, d, big, None) == L.DVQ_EINVAL  # top_L < 1
+    assert lib.dvq_pauli_decompose_batch(d, 4, 4, 257, d, d, f, d, big, None) == L.DVQ_EINVAL  # > 4^n
+    assert lib.dvq_pauli_decompose_batch(d, 4, 4, 8, d, d, None, d, big, None) == L.DVQ_EINVAL  # no error array
+    assert lib.dvq_pauli_decompose_batch(d, 13, 4, 8, d, d, f, d, big, None) == L.DVQ_EINVAL
+    need = lib.dvq_decompose_batch_workspace_bytes(4, 4)
+    assert need > lib.dvq_decompose_workspace_bytes(4)
+    assert lib.dvq_decompose_batch_workspace_bytes(4, 8) > need
+    assert lib.dvq_pauli_decompose_batch(d, 4, 4, 8, d, d, f, d, need - 1, None) == L.DVQ_ECAPACITY
+
+
 def test_grad_entry_points_reject_bad_input():
     lib = L.load()
     d = ctypes.c_void_p(16)

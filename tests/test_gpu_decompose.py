@@ -153,3 +153,36 @@ def test_pauli_sum_dense_reconstructs(n, L_):
     assert np.max(np.abs(got - want)) < 1e-13
     if n == 3:
         assert np.max(np.abs(got - A)) < 1e-13
+
+
+def test_batch_matches_single_calls():
+    """The batched top-L decomposition of a family equals one call per matrix
+    (n = 8, seven systems, L = 40: a cut inside some Toeplitz levels, where
+    the index tie-break decides) and the oracle."""
+    n, L_ = 8, 40
+    mats = [toeplitz(n, 1.0 + 0.05 * i, -0.45 + 0.04 * i) for i in range(7)]
+    mats[3] = random_symmetric(n, seed=3)
+    c, s, f = api.pauli_decompose_batch(_gpu(np.stack(mats)), L_)
+    for i, A in enumerate(mats):
+        c1, s1, f1 = api.pauli_decompose(_gpu(A), top_L=L_)
+        assert torch.equal(c[i], c1) and torch.equal(s[i], s1) and f[i] == f1
+        C = op.decompose_fwht(A)
+        keep = op.select_top(C, L_)
+        assert np.array_equal(_flat(s[i], n), keep)
+        assert abs(f[i] - op.frobenius_error(C, keep, A)) < 1e-12
+
+
+def test_device_toeplitz_batches_equal_host_recipe():
+    """The warm-start family built in device memory equals
+    workloads.toeplitz element by element, and decomposes to the same terms."""
+    from paper_2604_14435_amd.warmstart import decompose_batches, decompose_family, toeplitz_batches
+    from workloads import toeplitz_family
+
+    n = 7
+    ab = toeplitz_family(11, seed=3)
+    dev_mats = torch.cat(list(toeplitz_batches(ab, n, DEV, chunk=4)))
+    host = np.stack([toeplitz(n, a, b) for a, b in ab])
+    assert np.array_equal(dev_mats.cpu().numpy(), host)
+    c1, s1, f1 = decompose_batches(toeplitz_batches(ab, n, DEV, chunk=4), 24)
+    c2, s2, f2 = decompose_family((toeplitz(n, a, b) for a, b in ab), 24, DEV, chunk=5)
+    assert torch.equal(c1, c2) and torch.equal(s1, s2) and np.array_equal(f1, f2)

@@ -123,7 +123,7 @@ def test_warm_start_beats_random_init():
     n, layers, L_, S, S_test = 6, 3, 16, 384, 64
     an = api.AnsatzSpec(n, layers, "cnot")
     ab = toeplitz_family(S, seed=0)
-    coeffs, strings, _ = decompose_family([toeplitz(n, a, b) for a, b in ab], L_, DEV)
+    coeffs, strings, _ = decompose_family((toeplitz(n, a, b) for a, b in ab), L_, DEV)
     # common start: the solution of the centre system (1.0, -0.3)
     c0, s0, _ = decompose_family([toeplitz(n, 1.0, -0.3)], L_, DEV)
     th_r = torch.from_numpy(theta_uniform(an.P, seed=5)).to(DEV).unsqueeze(0)
