@@ -45,10 +45,10 @@ CSRC = os.path.join(ROOT, "paper_2604_14435_amd", "csrc")
 MEASURED_TRAFFIC = {
     "k_terms_fast<float,10,cz,plus>": {
         "sources": ["circuits_fast.hip", "wave_state.h", "circuits.h", "common.h"],
-        "sources_sha256": "cff488192784016b", "fetch_kib": 240.6, "write_kib": 2816.0},
+        "sources_sha256": "7fd0b08c02b2767b", "fetch_kib": 237.6, "write_kib": 2816.0},
     "k_fwht_fused<6,2> (n=12 dense)": {
         "sources": ["decompose.hip", "common.h"],
-        "sources_sha256": "a4a7ec1ef26ff715", "fetch_kib": 66005.5, "write_kib": 262222.2},
+        "sources_sha256": "6f82fc5f8a9e75fe", "fetch_kib": 66025.0, "write_kib": 262220.7},
 }
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131088.4, 1.0
 
