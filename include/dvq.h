@@ -199,6 +199,11 @@ int64_t dvq_circuit_count(int32_t n, int32_t L, int32_t cost_kind);
  *             X_j, S^dagger, H, measurement) are applied to a copy of that
  *             state -- the same results; shapes without a shared kernel fall
  *             back to the generic kernel.
+ *             The register-resident (literal and shared) kernels exist for
+ *             the local cost at n = 10, 11 (F32) and n = 10 (F64), with
+ *             either ladder and either b kind (a general b applies
+ *             U_b Z_j U_b^dagger through its Householder form); every other
+ *             shape runs the generic kernel.
  * Limits: n <= 12 (F64) / 13 (F32); B * circuits < 2^31.
  */
 dvq_status dvq_vqls_terms(const dvq_ansatz* ansatz, const double* theta, int32_t B,
@@ -250,7 +255,9 @@ dvq_status dvq_vqls_grad_shift(const dvq_ansatz* ansatz, const double* theta, in
  *   coeffs [L] and strings [L] shared by all rows (per_row_system = 0), or
  *          [B][L] each (per_row_system = 1: row r uses system r).
  *   C [B], grad [B][P] float64 outputs.
- * One workgroup per row; n <= 12.
+ * One workgroup per row; n <= 12.  Rows of the CZ-ladder ansatz at n = 10,
+ * 11 (F32) and n = 10 (F64) run as one wavefront each with both vectors in
+ * registers; other shapes use three LDS-resident vectors per row.
  */
 dvq_status dvq_vqls_grad_adjoint(const dvq_ansatz* ansatz, const double* theta, int32_t B,
                                  int32_t precision, const dvq_c128* coeffs,
