@@ -443,7 +443,14 @@ def pruning_sweep(api, dev):
         if L in paper:
             row["paper"] = {"frobenius_error_percent": paper[L][0], "median_solution_error_percent": paper[L][1]}
         rows.append(row)
-    return {"system": "n=10 tridiag(-1/3, 1, -1/3)", "rhs": "64 normalised Gaussian, seed 0", "rows": rows}
+    # resource counts (Fig. 2): circuits of one local-cost evaluation for
+    # n = 1..20 with every nonzero term of a tridiagonal Toeplitz matrix
+    # (2^n terms) and with the top 64
+    counts = [{"n": k, "terms_full": 1 << k, "circuits_full": int(api.circuit_count(k, 1 << k, "local")),
+               "terms_pruned": min(1 << k, 64), "circuits_pruned": int(api.circuit_count(k, min(1 << k, 64), "local"))}
+              for k in range(1, 21)]
+    return {"system": "n=10 tridiag(-1/3, 1, -1/3)", "rhs": "64 normalised Gaussian, seed 0", "rows": rows,
+            "circuit_counts_tridiagonal_toeplitz": counts}
 
 
 def main() -> int:
