@@ -132,3 +132,23 @@ def lbfgs(evaluate, theta0: np.ndarray, max_evals: int = 2000, target: float | N
         tr.stop = "target reached"
     tr.seconds = time.perf_counter() - t0
     return best[1], tr
+
+
+def lbfgs_refine(fast, precise, theta0: np.ndarray, max_evals: int = 4000, target: float | None = None,
+                 gtol: float = 1e-9) -> tuple[np.ndarray, Trace]:
+    """Mixed precision: L-BFGS-B on the `fast` evaluator (complex64 states)
+    until it stops -- near flat regions the float32 cost no longer resolves
+    the decrease of a step -- then from its best point on the `precise`
+    evaluator (complex128 adjoint), within one evaluation budget.  The
+    trace concatenates both phases (iterates, evaluations, seconds)."""
+    th1, t1 = lbfgs(fast, theta0, max_evals=max_evals, target=target, gtol=gtol)
+    if t1.stop == "target reached" or t1.evals >= max_evals:
+        return th1, t1
+    th2, t2 = lbfgs(precise, th1, max_evals=max_evals - t1.evals, target=target, gtol=gtol)
+    tr = Trace(costs=t1.costs + t2.costs, thetas=t1.thetas + t2.thetas,
+               iter_evals=t1.iter_evals + [t1.evals + e for e in t2.iter_evals],
+               iter_seconds=t1.iter_seconds + [t1.seconds + x for x in t2.iter_seconds],
+               evals=t1.evals + t2.evals, seconds=t1.seconds + t2.seconds,
+               stop=f"float32: {t1.stop[:40]}; float64: {t2.stop[:40]}")
+    return (th2 if min(t2.costs, default=np.inf) <= min(t1.costs) else th1), tr
+

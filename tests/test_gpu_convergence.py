@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 from paper_2604_14435_amd import api  # noqa: E402
-from paper_2604_14435_amd.optim import Evaluator, lbfgs  # noqa: E402
+from paper_2604_14435_amd.optim import Evaluator, lbfgs, lbfgs_refine  # noqa: E402
 
 DEV = "cuda:0"
 
@@ -76,3 +76,22 @@ def test_target_stops_early():
     first = next(i for i, v in enumerate(full.costs) if v <= target)
     _, tr = lbfgs(ev, th0, max_evals=500, target=target)
     assert tr.stop == "target reached" and tr.evals == first + 1
+
+
+def test_refinement_continues_after_float32_stalls():
+    """n = 10, L = 64, RY + CNOT ladder from V|0> = b: complex64 L-BFGS stops
+    in a flat region where its cost no longer resolves the steps; the
+    complex128 phase of the mixed driver continues to a lower cost."""
+    n = 10
+    A = toeplitz(n, 1.0, -0.45)
+    c, s, _ = api.pauli_decompose(torch.from_numpy(A).to(DEV), tau=0.01)
+    an = api.AnsatzSpec(n, 4, "cnot")
+    th0 = np.zeros(an.P)
+    th0[:n] = np.pi / 2
+    ev32, ev64 = Evaluator(an, c, s, "f32-adjoint"), Evaluator(an, c, s, "f64-adjoint")
+    _, t32 = lbfgs(ev32, th0, max_evals=600, gtol=1e-12)
+    assert t32.evals < 600  # stopped on its own
+    th, tr = lbfgs_refine(ev32, ev64, th0, max_evals=600, gtol=1e-12)
+    assert "float64" in tr.stop and tr.evals > t32.evals
+    assert min(tr.costs) < min(t32.costs) - 1e-4
+    assert len(tr.iter_evals) == len(tr.thetas) and tr.iter_evals == sorted(tr.iter_evals)
