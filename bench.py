@@ -25,6 +25,7 @@ import argparse
 import json
 import math
 import os
+import platform
 import sys
 import time
 
@@ -83,41 +84,248 @@ def circuit_flops(n: int, layers: int) -> int:
     return (1 << (n + 1)) * (6 * n * layers + 4 + 4)
 
 
-def cpu_baseline(seconds: float):
-    """The oracle's gate-by-gate circuits on the host (one core), on a bounded
-    sample of the same evaluation (real and imaginary circuits of beta and
-    delta terms in the order of the evaluation, strided)."""
-    import numpy as np
+_SAMPLE = {}
 
-    from oracle import circuit as qc
+
+def _sample_setup():
+    """Kept terms and angles of the n=10 L=64 evaluation, for the oracle."""
     from oracle import pauli as op
     from workloads import theta_uniform, toeplitz
 
-    n, layers = N_QUBITS, LAYERS
-    C = op.decompose_fwht(toeplitz(n, DIAG, OFFDIAG))
+    C = op.decompose_fwht(toeplitz(N_QUBITS, DIAG, OFFDIAG))
     keep = op.select_tau(C, TAU)
-    _, xs, zs = op.kept_terms(C, keep)
-    L = len(keep)
-    th = theta_uniform(n * layers, seed=0)
-    total = 2 * (n + 1) * L * L
-    done = 0
+    coeffs, xs, zs = op.kept_terms(C, keep)
+    _SAMPLE.update(coeffs=coeffs, xs=xs, zs=zs, L=len(keep), th=theta_uniform(N_QUBITS * LAYERS, seed=0))
+
+
+def _oracle_circuit(c: int) -> float:
+    """<Z_a> of circuit c of the evaluation: c = 2 u + (imaginary part),
+    u = j L^2 + l L + m with j = 0 the beta term and j >= 1 the delta term
+    of qubit j - 1."""
+    from oracle import circuit as qc
+
+    n, layers = N_QUBITS, LAYERS
+    xs, zs, L, th = _SAMPLE["xs"], _SAMPLE["zs"], _SAMPLE["L"], _SAMPLE["th"]
+    part, u = c & 1, c >> 1
+    jj, lm = divmod(u, L * L)
+    l, m = divmod(lm, L)
+    sl, sm = (int(xs[l]), int(zs[l])), (int(xs[m]), int(zs[m]))
+    if jj == 0:
+        return qc.beta_circuit(th, n, layers, "cz", sl, sm, bool(part))
+    return qc.delta_circuit(th, n, layers, "cz", sl, sm, jj - 1, bool(part))
+
+
+def _oracle_range(bounds):
+    """Circuits first .. stop - 1 of the evaluation, in order."""
+    first, stop = bounds
+    return [_oracle_circuit(c) for c in range(first, stop)]
+
+
+def _oracle_circuits(args):
+    """Run the circuits k = first, first + every, ... of the strided order
+    c_k = 7919 k mod total for `seconds`; returns (circuits, seconds)."""
+    first, every, seconds = args
+    total = 2 * (N_QUBITS + 1) * _SAMPLE["L"] ** 2
+    done, k = 0, first
     t0 = time.perf_counter()
-    c = 0
     while time.perf_counter() - t0 < seconds:
-        part, u = c & 1, (c >> 1)
-        jj, lm = divmod(u, L * L)
-        l, m = divmod(lm, L)
-        sl, sm = (int(xs[l]), int(zs[l])), (int(xs[m]), int(zs[m]))
-        if jj == 0:
-            qc.beta_circuit(th, n, layers, "cz", sl, sm, bool(part))
-        else:
-            qc.delta_circuit(th, n, layers, "cz", sl, sm, jj - 1, bool(part))
+        _oracle_circuit((k * 7919) % total)
         done += 1
-        c = (c + 7919) % total
-    el = time.perf_counter() - t0
-    return {"value": done / el, "unit": "circuits/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} of the {total} circuits of one n=10 L=64 cost evaluation, "
-                      f"gate by gate in NumPy float64, {el:.1f} s on one core"}
+        k += every
+    return done, time.perf_counter() - t0
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def small_workload_oracle():
+    """The n=3 workload in full on the oracle, one core: every Hadamard-test
+    circuit of the global cost at each shift-rule point, 50 gradient-descent
+    steps (eta = 0.1), theta from seed 0."""
+    from oracle import cost as oc
+    from oracle import pauli as op
+    from workloads import theta_uniform, toeplitz
+
+    n, layers = 3, 2
+    C = op.decompose_fwht(toeplitz(n, 1.0, -0.4))
+    keep = op.select_tau(C, 0.01)
+    c, xs, zs = op.kept_terms(C, keep)
+    th0 = theta_uniform(n * layers, seed=0)
+    parts = lambda t: oc.parts_theta_circuits(t, c, xs, zs, n, layers, "cz", "global")  # noqa: E731
+    t0 = time.perf_counter()
+    _, costs = oc.gradient_descent(th0, lambda t: oc.grad_parameter_shift(parts, t, n, "global"), 0.1, 50)
+    return {"seconds": time.perf_counter() - t0, "costs": [float(x) for x in costs], "L": len(keep)}
+
+
+BF16_MFMA_PEAK = 2500.0  # TFLOP/s: MI355X dense bfloat16 matrix-core peak
+
+
+def mlp_flops(B: int, d_in: int, H: int, D: int, backward: bool) -> int:
+    """Useful flops of the MLP's GEMMs at batch B (no padding counted):
+    forward X W1, H1 W2, H2 W3; backward dW3, dZ2, dW2, dZ1, dW1."""
+    fwd = 2 * B * (d_in * H + H * H + H * D)
+    return fwd + (2 * B * (2 * D * H + 2 * H * H + H * d_in) if backward else 0)
+
+
+def mlp_timing(api, dev, d_in=2, H=256, D=40, B=256, family=4096, reps=200):
+    """The warm-start MLP on the bfloat16 matrix cores: one training step
+    (forward, loss gradient, backward, AdamW update) at the training batch,
+    and one forward pass over a whole 4096-system family, timed with events
+    on the launch stream.  MFMA utilisation = useful GEMM flops / time / the
+    dense bfloat16 peak: at these sizes the kernels are launch-latency bound,
+    so this is a utilisation figure, not a roofline claim."""
+    import torch
+
+    g = torch.Generator().manual_seed(0)
+    shape = api.mlp_shape(d_in, H, D)
+    P = api.mlp_param_count(shape)
+    params = (torch.rand(P, generator=g) * 0.1 - 0.05).to(dev)
+    grads, m, v = torch.empty_like(params), torch.zeros_like(params), torch.zeros_like(params)
+    X = torch.randn(B, d_in, generator=g).to(dev)
+    T = torch.randn(B, D, generator=g).to(dev)
+    Xf = torch.randn(family, d_in, generator=g).to(dev)
+    fwd = api.mlp_forward(shape, params, X)
+    lg = api.mlp_loss_grad(fwd[0], T)
+    ws = torch.empty(2 * B * H * 4, dtype=torch.uint8, device=dev)
+    ffam = api.mlp_forward(shape, params, Xf)
+    stream = torch.cuda.current_stream(dev)
+
+    def train(t):
+        api.mlp_forward(shape, params, X, out=fwd)
+        api.mlp_loss_grad(fwd[0], T, out=lg)
+        api.mlp_backward(shape, params, X, fwd[1], fwd[2], lg[0], ws, out=grads)
+        api.adamw_step(params, grads, m, v, t, 1e-4)
+
+    def infer(_):
+        api.mlp_forward(shape, params, Xf, out=ffam)
+
+    res = {}
+    for name, fn, flops in (("training_step_b256", train, mlp_flops(B, d_in, H, D, True)),
+                            ("forward_b4096", infer, mlp_flops(family, d_in, H, D, False))):
+        for t in range(10):
+            fn(t + 1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for t in range(reps):
+            fn(t + 11)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        tf = flops / (us * 1e-6) / 1e12
+        res[name] = {"us": round(us, 2), "gemm_mflop": round(flops / 1e6, 2), "tflops": round(tf, 3),
+                     "mfma_utilisation": round(tf / BF16_MFMA_PEAK, 6)}
+    res["peak_tflops"] = BF16_MFMA_PEAK
+    res["shape"] = f"{d_in}->{H}->{H}->{D}, bfloat16 operands, float32 accumulation"
+    return res
+
+
+def small_workload_gpu(api, dev, oracle_run):
+    """The n=3 workload on the GPU (complex128 shift rule, the gradient-descent
+    update on the device), timed from the first evaluation to the last update,
+    its costs against the oracle's."""
+    import numpy as np
+    import torch
+
+    from workloads import theta_uniform, toeplitz
+
+    n, layers, eta, steps = 3, 2, 0.1, 50
+    A = torch.from_numpy(toeplitz(n, 1.0, -0.4)).to(dev)
+    c, s, _ = api.pauli_decompose(A, tau=0.01)
+    an = api.AnsatzSpec(n, layers, "cz")
+    ws = api.ShiftWorkspace(an, c.shape[0], "global", dev)
+    costs = torch.empty(steps, dtype=torch.float64, device=dev)
+    best = None
+    for _ in range(3):
+        theta = torch.from_numpy(theta_uniform(n * layers, seed=0)).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            C, g = api.vqls_grad_shift(an, theta, c, s, "global", "f64", workspace=ws)
+            costs[k:k + 1].copy_(C)
+            api.gd_step(theta, g, eta)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        best = el if best is None else min(best, el)
+    got = costs.cpu().numpy()
+    diff = float(np.max(np.abs(got - np.array(oracle_run["costs"][:steps]))))
+    return {"gpu_seconds": round(best, 5), "oracle_seconds": round(oracle_run["seconds"], 3),
+            "speedup": round(oracle_run["seconds"] / best, 1), "max_cost_difference": diff,
+            "what": "n=3 Toeplitz (1, -0.4), tau=0.01, 2 layers RY+CZ, global cost, 50 shift-rule "
+                    "gradient-descent steps (eta=0.1) from seed 0; GPU: best of 3, oracle: one core"}
+
+
+def cpu_baseline(seconds: float, pool_seconds: float, full_limit: float):
+    """The oracle on the host before the GPU is touched: its gate-by-gate
+    circuits of the n=10 L=64 cost evaluation (real and imaginary circuits of
+    the beta and delta terms) on one core (a bounded, strided sample) and on
+    every core through a fork pool (at most 16 workers, the CPU share of one
+    GPU): the whole evaluation and its cost when the single-core rate says it
+    finishes within `full_limit` seconds, else a strided sample of
+    `pool_seconds`; the dense n=12 FWHT decomposition in full; the n=3
+    workload in full."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    from oracle import cost as oc
+    from oracle import pauli as op
+    from workloads import random_symmetric
+
+    _sample_setup()
+    L = _SAMPLE["L"]
+    total = 2 * (N_QUBITS + 1) * L * L
+    one, el1 = _oracle_circuits((0, 1, seconds))
+    rate1 = one / el1
+    progress(f"oracle circuits, one core: {rate1:.1f} circuits/s")
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    full = None
+    with mp.get_context("fork").Pool(workers) as pool:
+        if total / (rate1 * workers) <= full_limit:
+            step = -(-total // (8 * workers))
+            chunks = [(c0, min(c0 + step, total)) for c0 in range(0, total, step)]
+            t0 = time.perf_counter()
+            vals = np.array([v for part in pool.map(_oracle_range, chunks) for v in part])
+            el = time.perf_counter() - t0
+            terms = (vals[0::2] + 1j * vals[1::2]).reshape(N_QUBITS + 1, L, L)
+            cost = oc.cost_from_terms(_SAMPLE["coeffs"], terms[0], terms[1:], N_QUBITS, "local")
+            full = {"seconds": round(el, 3), "cost": cost}
+            rate, done_all = total / el, total
+            sample = (f"the whole n=10 L=64 cost evaluation ({total} circuits) and its cost, gate by gate "
+                      f"in NumPy float64, {workers} processes, {el:.1f} s")
+        else:
+            res = pool.map(_oracle_circuits, [(w, workers, pool_seconds) for w in range(workers)])
+            rate, done_all = sum(d / e for d, e in res), sum(d for d, _ in res)
+            sample = (f"{done_all} of the {total} circuits of one n=10 L=64 cost evaluation (strided), "
+                      f"gate by gate in NumPy float64, {workers} processes for {pool_seconds:.0f} s")
+    progress(f"oracle circuits, {workers} processes: {rate:.1f} circuits/s")
+    A = random_symmetric(12, seed=0)
+    t0 = time.perf_counter()
+    op.decompose_fwht(A)
+    fwht_s = time.perf_counter() - t0
+    del A
+    small = small_workload_oracle()
+    progress(f"oracle n=3 workload: {small['seconds']:.1f} s")
+    P = N_QUBITS * LAYERS
+    out = {"value": round(rate, 2), "unit": "circuits/s", "cores": workers, "kind": "oracle", "sample": sample,
+           "cpu_model": _cpu_model(), "nproc": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0)),
+           "single_core": {"value": round(rate1, 2), "unit": "circuits/s", "cores": 1,
+                           "sample": f"{one} circuits (strided over the evaluation) in {el1:.1f} s"},
+           "cost_evaluation_s": full["seconds"] if full else None,
+           "extrapolated_s": {"cost_evaluation_one_core": round(total / rate1, 1),
+                              "shift_rule_iteration": round((2 * P + 1) * total / rate, 1)},
+           "fwht_n12_dense_s": round(fwht_s, 3),
+           "small_workload": {"seconds": round(small["seconds"], 3), "cores": 1,
+                              "what": f"n=3, L={small['L']}, global cost, 50 shift-rule GD steps, every circuit"}}
+    return out, small, full
 
 
 def warm_start_experiment(api, dev, n, layers, eta, budget, epochs, family_iters, seed_rand=0):
@@ -470,6 +678,69 @@ def heleshaw_run(api, dev, reps=3, iters=200):
             "condition_number": float(np.linalg.cond(A))}
 
 
+def adjoint_workload(api, dev, reps=5):
+    """n = 10, tridiag(-0.45, 1, -0.45), tau = 0.005 -> L = 128, 6 layers
+    RY + CZ ladder (60 angles), local cost, b = |+>, theta from seed 0: one
+    iteration's cost and gradient in three forms -- every circuit in
+    complex64 plus the complex64 adjoint gradient (fast form), the complex128
+    adjoint alone, and the complex128 parameter-shift rule ((2P + 1) x
+    360,448 circuits, the plain form) -- with the gradients against the
+    shift rule's."""
+    import torch
+
+    from workloads import theta_uniform, toeplitz
+
+    n, layers = 10, 6
+    A = torch.from_numpy(toeplitz(n, DIAG, OFFDIAG)).to(dev)
+    coeffs, strings, _ = api.pauli_decompose(A, tau=0.005)
+    L = int(coeffs.shape[0])
+    an = api.AnsatzSpec(n, layers, "cz")
+    P = an.P
+    circuits = int(api.circuit_count(n, L, "local"))
+    th = torch.from_numpy(theta_uniform(P, seed=0)).to(dev)
+    beta = torch.empty((1, L, L), dtype=torch.complex128, device=dev)
+    delta = torch.empty((1, n, L, L), dtype=torch.complex128, device=dev)
+    C, parts = torch.empty(1, dtype=torch.float64, device=dev), torch.empty((1, 2), dtype=torch.complex128, device=dev)
+    Ca, ga = torch.empty(1, dtype=torch.float64, device=dev), torch.empty((1, P), dtype=torch.float64, device=dev)
+    Cd, gd = torch.empty(1, dtype=torch.float64, device=dev), torch.empty((1, P), dtype=torch.float64, device=dev)
+    ws = api.ShiftWorkspace(an, L, "local", dev)
+    Cs, gs = torch.empty(1, dtype=torch.float64, device=dev), torch.empty(P, dtype=torch.float64, device=dev)
+
+    def fast():
+        api.vqls_terms(an, th, strings, "local", "f32", out=(beta, delta))
+        api.vqls_cost(coeffs, n, "local", beta, delta, out=(C, parts))
+        api.vqls_grad_adjoint(an, th, coeffs, strings, "local", "f32", out=(Ca, ga))
+
+    def adj64():
+        api.vqls_grad_adjoint(an, th, coeffs, strings, "local", "f64", out=(Cd, gd))
+
+    def shift():
+        api.vqls_grad_shift(an, th, coeffs, strings, "local", "f64", workspace=ws, out=(Cs, gs))
+
+    def timed(fn, r):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(r):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / r
+
+    t_fast, t_adj, t_shift = timed(fast, reps), timed(adj64, reps), timed(shift, 1)
+    g_ref = gs.double()
+    return {"system": "n=10 tridiag(-0.45, 1, -0.45), tau=0.005", "L": L, "layers": layers, "P": P,
+            "circuits_per_evaluation": circuits,
+            "s_per_iteration": {"fp32_circuits_plus_fp32_adjoint": round(t_fast, 6),
+                                "fp64_adjoint": round(t_adj, 6), "plain_fp64_shift": round(t_shift, 4)},
+            "circuits_per_s": {"fp32": round(circuits / t_fast, 1),
+                               "plain_fp64_shift": round((2 * P + 1) * circuits / t_shift, 1)},
+            "per_iter_speedup_vs_plain": round(t_shift / t_fast, 1),
+            "grad_max_abs_vs_shift": {"fp64_adjoint": float(torch.max(torch.abs(gd[0] - g_ref)).item()),
+                                      "fp32_adjoint": float(torch.max(torch.abs(ga[0] - g_ref)).item())},
+            "cost_abs_vs_shift": {"fp64_adjoint": abs(Cd.item() - Cs.item()),
+                                  "fp32_circuits": abs(C.item() - Cs.item())}}
+
+
 def pruning_sweep(api, dev):
     """Accuracy of the pruned operator (Section III-B): n = 10,
     tridiag(-1/3, 1, -1/3), the paper's tau list.  Decomposition, selection
@@ -517,7 +788,12 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--plain-steps", type=int, default=3)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="oracle circuit sample on one core")
+    ap.add_argument("--cpu-pool-seconds", type=float, default=6.0,
+                    help="oracle circuit sample on every usable core")
+    ap.add_argument("--cpu-full-limit", type=float, default=60.0,
+                    help="run the whole oracle cost evaluation on every core if it takes at most this long")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (calibrates HBM counters)")
@@ -538,6 +814,11 @@ def main() -> int:
     from paper_2604_14435_amd import api
     from workloads import theta_uniform, toeplitz
 
+    cpu = small_oracle = full_oracle = None
+    if not args.no_cpu_baseline:
+        # before the GPU is touched: the pool forks this process
+        cpu, small_oracle, full_oracle = cpu_baseline(args.cpu_seconds, args.cpu_pool_seconds,
+                                                      args.cpu_full_limit)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.copy_mib > 0:
@@ -726,6 +1007,8 @@ def main() -> int:
     }
     progress("precision comparison done")
     out["pruning_sweep"] = pruning_sweep(api, dev)
+    out["adjoint_L128"] = adjoint_workload(api, dev)
+    progress("L=128 adjoint workload done")
     if not args.no_heleshaw:
         out["heleshaw"] = heleshaw_run(api, dev)
         progress("Hele-Shaw-like system done")
@@ -735,8 +1018,16 @@ def main() -> int:
         progress("warm start and time to solution done")
         out["four_qubit_fidelity"] = four_qubit_fidelity(api, dev)
         progress("four-qubit fidelity run done")
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    out["mlp"] = mlp_timing(api, dev)
+    progress("MLP timing done")
+    if cpu is not None:
+        out["small_workload"] = small_workload_gpu(api, dev, small_oracle)
+        progress("n=3 workload on the GPU done")
+        if full_oracle is not None:
+            cpu["cost_vs_gpu"] = {"oracle": full_oracle["cost"], "gpu_fp64": c64.item(), "gpu_fp32": c32.item(),
+                                  "abs_fp64": abs(c64.item() - full_oracle["cost"]),
+                                  "abs_fp32": abs(c32.item() - full_oracle["cost"])}
+        out["cpu_baseline"] = cpu
     print(json.dumps(out))
     return 0
 
