@@ -46,8 +46,8 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
     const int r = lane & 15, kb = (lane >> 4) * 8;
     const int m = tm * 16 + r, n = tn * 16 + r;
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < g.K; k0 += 32) {
-        bf16x8 a, b;
+    // operands of k-step k0 (zero outside the matrices)
+    auto load = [&](int k0, bf16x8& a, bf16x8& b) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int k = k0 + kb + j;
@@ -56,7 +56,16 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
             a[j] = to_bf16(av);
             b[j] = to_bf16(bv);
         }
+    };
+    // the loads of step k0 + 32 are issued before the product of step k0
+    bf16x8 a, b;
+    load(0, a, b);
+    for (int k0 = 0; k0 < g.K; k0 += 32) {
+        bf16x8 an, bn;
+        if (k0 + 32 < g.K) load(k0 + 32, an, bn);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+        a = an;
+        b = bn;
     }
     const int nn = tn * 16 + (lane & 15);
 #pragma unroll
@@ -79,13 +88,35 @@ static dvq_status gemm(const GemmArgs& g, hipStream_t s) {
     return DVQ_OK;
 }
 
-// out[n] = sum_m X[m * ld + n] (float32, fixed order), one thread per column.
-__global__ void k_colsum(const float* __restrict__ X, int M, int N, int64_t ld, float* __restrict__ out) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
+// out[n] = sum_m X[m * ld + n] (float32, fixed order).  A workgroup covers
+// 64 columns with 16 row groups: wave g sums rows g, g + 16, ... (lanes read
+// 64 consecutive columns of a row), then lane c of wave 0 adds the 16
+// partials of its column in group order.  One thread per column would chain
+// M dependent loads; this chains M / 16.
+constexpr int kColsumGroups = 16;
+
+__global__ void __launch_bounds__(64 * kColsumGroups)
+k_colsum(const float* __restrict__ X, int M, int N, int64_t ld, float* __restrict__ out) {
+    __shared__ float part[kColsumGroups][64];
+    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int n = blockIdx.x * 64 + c;
     float s = 0.f;
-    for (int m = 0; m < M; ++m) s += X[m * ld + n];
-    out[n] = s;
+    if (n < N)
+        for (int m = g; m < M; m += kColsumGroups) s += X[(int64_t)m * ld + n];
+    part[g][c] = s;
+    __syncthreads();
+    if (g == 0 && n < N) {
+        float t = 0.f;
+#pragma unroll
+        for (int k = 0; k < kColsumGroups; ++k) t += part[k][c];
+        out[n] = t;
+    }
+}
+
+static dvq_status colsum(const float* X, int M, int N, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_colsum, dim3((N + 63) / 64), dim3(64 * kColsumGroups), 0, s, X, M, N, (int64_t)N, out);
+    DVQ_CHECK_LAUNCH("k_colsum");
+    return DVQ_OK;
 }
 
 // dY = sin(Y - T) / count; loss = mean(1 - cos(Y - T)) in float64.
@@ -227,9 +258,7 @@ dvq_status dvq_mlp_backward(const dvq_mlp_shape* shape, const float* params, con
     hipStream_t hs = stream_of(stream);
     // dW3 = dY^T H2 ; db3 = colsum(dY)
     if ((st = gemm(ga(D, H, B, dY, 1, D, H2, H, 1, dparams + o.W3, H), hs)) != DVQ_OK) return st;
-    hipLaunchKernelGGL(k_colsum, dim3((D + 255) / 256), dim3(256), 0, hs, dY, B, D, (int64_t)D,
-                       dparams + o.b3);
-    DVQ_CHECK_LAUNCH("k_colsum");
+    if ((st = colsum(dY, B, D, dparams + o.b3, hs)) != DVQ_OK) return st;
     // dZ2 = (dY W3) * [H2 > 0]
     GemmArgs g = ga(B, H, D, dY, D, 1, params + o.W3, H, 1, dZ2, H);
     g.mask = H2;
@@ -237,9 +266,7 @@ dvq_status dvq_mlp_backward(const dvq_mlp_shape* shape, const float* params, con
     if ((st = gemm(g, hs)) != DVQ_OK) return st;
     // dW2 = dZ2^T H1 ; db2 = colsum(dZ2)
     if ((st = gemm(ga(H, H, B, dZ2, 1, H, H1, H, 1, dparams + o.W2, H), hs)) != DVQ_OK) return st;
-    hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, hs, dZ2, B, H, (int64_t)H,
-                       dparams + o.b2);
-    DVQ_CHECK_LAUNCH("k_colsum");
+    if ((st = colsum(dZ2, B, H, dparams + o.b2, hs)) != DVQ_OK) return st;
     // dZ1 = (dZ2 W2) * [H1 > 0]
     g = ga(B, H, H, dZ2, H, 1, params + o.W2, H, 1, dZ1, H);
     g.mask = H1;
@@ -248,10 +275,7 @@ dvq_status dvq_mlp_backward(const dvq_mlp_shape* shape, const float* params, con
     // dW1 = dZ1^T X ; db1 = colsum(dZ1)
     if ((st = gemm(ga(H, s.d_in, B, dZ1, 1, H, X, s.d_in, 1, dparams + o.W1, s.d_in), hs)) != DVQ_OK)
         return st;
-    hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, hs, dZ1, B, H, (int64_t)H,
-                       dparams + o.b1);
-    DVQ_CHECK_LAUNCH("k_colsum");
-    return DVQ_OK;
+    return colsum(dZ1, B, H, dparams + o.b1, hs);
 }
 
 dvq_status dvq_adamw_step(float* params, const float* grads, float* m, float* v, int64_t count,
