@@ -202,14 +202,38 @@ int64_t dvq_circuit_count(int32_t n, int32_t L, int32_t cost_kind);
  *             The register-resident (literal and shared) kernels exist for
  *             the local cost at n = 10, 11 (F32) and n = 10 (F64), with
  *             either ladder and either b kind (a general b applies
- *             U_b Z_j U_b^dagger through its Householder form); every other
- *             shape runs the generic kernel.
+ *             U_b Z_j U_b^dagger through its Householder form), and run
+ *             the beta circuits of the global cost at the same shapes (its
+ *             gamma circuits, with a controlled V(theta), run on the
+ *             generic kernel); every other shape runs the generic kernel.
  * Limits: n <= 12 (F64) / 13 (F32); B * circuits < 2^31.
  */
 dvq_status dvq_vqls_terms(const dvq_ansatz* ansatz, const double* theta, int32_t B,
                           int32_t precision, const dvq_pauli* strings, int32_t L,
                           int32_t b_kind, const double* b, int32_t cost_kind, int32_t exec,
                           dvq_c128* beta, dvq_c128* other, dvq_stream stream);
+
+/*
+ * Several right-hand sides with the same A and angles: beta_lm involves
+ * neither b nor U_b (Section II-C), so its 2 L^2 circuits per row run once,
+ * and only the b-dependent circuits (delta for the local cost, gamma for the
+ * global cost) run once per right-hand side -- the amortisation over
+ * right-hand sides sharing A that the paper's conclusion points to, carried
+ * from the decomposition to the circuits.
+ *   b      [R][2^n] float64 unit vectors (device), one per right-hand side
+ *          (as DVQ_B_VECTOR in dvq_vqls_terms).  1 <= R <= 65536.
+ *   beta   [B][L][L] output, written once.
+ *   other  [R][B][n][L][L] (local) or [R][B][L] (global) output: block r
+ *          holds what dvq_vqls_terms writes for b_r.
+ * Every other argument as in dvq_vqls_terms; the values equal those of R
+ * separate dvq_vqls_terms calls with b_kind = DVQ_B_VECTOR (the same kernels
+ * compute every circuit).  Errors: DVQ_EINVAL for R outside 1..65536, a NULL
+ * b, or any argument dvq_vqls_terms rejects; nothing is launched then.
+ */
+dvq_status dvq_vqls_terms_rhs(const dvq_ansatz* ansatz, const double* theta, int32_t B,
+                              int32_t precision, const dvq_pauli* strings, int32_t L, int32_t R,
+                              const double* b, int32_t cost_kind, int32_t exec, dvq_c128* beta,
+                              dvq_c128* other, dvq_stream stream);
 
 /*
  * Cost from the terms (float64): Psi = sum_lm conj(c_l) c_m beta_lm;

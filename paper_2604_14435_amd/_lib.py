@@ -53,6 +53,8 @@ SIGNATURES = {
     "dvq_circuit_count": (c_int64, [c_int32, c_int32, c_int32]),
     "dvq_vqls_terms": (c_int32, [_A, _V, c_int32, c_int32, _V, c_int32, c_int32, _V, c_int32,
                                  c_int32, _V, _V, _V]),
+    "dvq_vqls_terms_rhs": (c_int32, [_A, _V, c_int32, c_int32, _V, c_int32, c_int32, _V, c_int32,
+                                     c_int32, _V, _V, _V]),
     "dvq_vqls_cost": (c_int32, [_V, c_int32, c_int32, c_int32, _V, _V, c_int32, _V, _V, _V]),
     "dvq_grad_shift_workspace_bytes": (c_size_t, [_A, c_int32, c_int32]),
     "dvq_vqls_grad_shift": (c_int32, [_A, _V, c_int32, _V, _V, c_int32, c_int32, _V, c_int32,

@@ -52,6 +52,30 @@ def _cuda(t: torch.Tensor, dtype, name: str) -> torch.Tensor:
     return t.contiguous()
 
 
+def _shape(t: torch.Tensor, shape, name: str) -> torch.Tensor:
+    """The kernels index inputs by the sizes they are given: check them here."""
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def _out(t, shape, dtype, name: str) -> torch.Tensor:
+    """A caller-supplied output: CUDA, contiguous, of the exact dtype and shape
+    the kernels write (they cannot check a pointer's extent)."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    return _shape(t, shape, name)
+
+
+def _square(A: torch.Tensor) -> torch.Tensor:
+    """A [N, N] with N a power of two."""
+    if A.dim() != 2 or A.shape[0] != A.shape[1] or A.shape[0] < 2 or A.shape[0] & (A.shape[0] - 1):
+        raise ValueError(f"A must be [N, N] with N = 2^n >= 2, got {tuple(A.shape)}")
+    return A
+
+
 def _b_args(b_kind: str, b):
     if b_kind == "plus":
         return L.DVQ_B_PLUS, None
@@ -68,16 +92,15 @@ def decompose_workspace(n: int, device) -> torch.Tensor:
 def pauli_decompose_dense(A: torch.Tensor, out: torch.Tensor | None = None,
                           workspace: torch.Tensor | None = None) -> torch.Tensor:
     """All 4^n coefficients, complex128 [N, N] indexed [x, z]."""
-    A = _cuda(A, torch.float64, "A")
+    A = _square(_cuda(A, torch.float64, "A"))
     N = A.shape[0]
     n = N.bit_length() - 1
     ws = decompose_workspace(n, A.device) if workspace is None else workspace
     if out is None:
         out = torch.empty((N, N), dtype=torch.complex128, device=A.device)
-    elif tuple(out.shape) != (N, N) or not out.is_contiguous():
-        raise ValueError(f"out must be a contiguous [{N}, {N}] tensor")
-    L.call("dvq_pauli_decompose_dense", _p(A), n, _p(_cuda(out, torch.complex128, "out")), _p(ws), ws.numel(),
-           _stream(A))
+    else:
+        _out(out, (N, N), torch.complex128, "out")
+    L.call("dvq_pauli_decompose_dense", _p(A), n, _p(out), _p(ws), ws.numel(), _stream(A))
     return out
 
 
@@ -85,7 +108,7 @@ def pauli_decompose(A: torch.Tensor, tau: float | None = None, top_L: int | None
                     capacity: int = 65536):
     """Kept terms in ranking order: (coeffs complex128 [L], strings int32 [L, 2] = (x, z),
     relative Frobenius error)."""
-    A = _cuda(A, torch.float64, "A")
+    A = _square(_cuda(A, torch.float64, "A"))
     N = A.shape[0]
     n = N.bit_length() - 1
     lib = L.load()
@@ -105,6 +128,9 @@ def pauli_decompose_batch(A: torch.Tensor, top_L: int, workspace: torch.Tensor |
     """Top-L terms of each of B matrices A [B, N, N]: (coeffs complex128 [B, L],
     strings int32 [B, L, 2], relative Frobenius errors float64 numpy [B])."""
     A = _cuda(A, torch.float64, "A")
+    if A.dim() != 3:
+        raise ValueError(f"A must be [B, N, N], got {tuple(A.shape)}")
+    _square(A[0])
     B, N = A.shape[0], A.shape[1]
     n = N.bit_length() - 1
     need = L.load().dvq_decompose_batch_workspace_bytes(n, B)
@@ -122,6 +148,7 @@ def pauli_sum_dense(coeffs: torch.Tensor, strings: torch.Tensor, n: int) -> torc
     """sum_l c_l P_l as a dense complex128 [2^n, 2^n] matrix."""
     coeffs = _cuda(coeffs, torch.complex128, "coeffs")
     strings = _cuda(strings, torch.int32, "strings")
+    _shape(strings, (coeffs.shape[0], 2), "strings")
     N = 1 << n
     out = torch.empty((N, N), dtype=torch.complex128, device=coeffs.device)
     L.call("dvq_pauli_sum_dense", _p(coeffs), _p(strings), coeffs.shape[0], n, _p(out), _stream(coeffs))
@@ -143,16 +170,49 @@ def vqls_terms(ansatz: AnsatzSpec, theta: torch.Tensor, strings: torch.Tensor, k
         theta = theta.unsqueeze(0)
     strings = _cuda(strings, torch.int32, "strings")
     B, Lt, n = theta.shape[0], strings.shape[0], ansatz.n
+    _shape(theta, (B, ansatz.P), "theta")
+    _shape(strings, (Lt, 2), "strings")
+    oshape = (B, n, Lt, Lt) if kind == "local" else (B, Lt)
     if out is None:
         beta = torch.empty((B, Lt, Lt), dtype=torch.complex128, device=theta.device)
-        oshape = (B, n, Lt, Lt) if kind == "local" else (B, Lt)
         other = torch.empty(oshape, dtype=torch.complex128, device=theta.device)
     else:
-        beta, other = out
+        beta = _out(out[0], (B, Lt, Lt), torch.complex128, "beta")
+        other = _out(out[1], oshape, torch.complex128, "other")
     bk, bt = _b_args(b_kind, b)
+    if bt is not None:
+        _shape(bt, (1 << n,), "b")
     a = ansatz.c()
     L.call("dvq_vqls_terms", ctypes.byref(a), _p(theta), B, PRECISIONS[precision], _p(strings), Lt,
            bk, _p(bt), KINDS[kind], EXECS[exec_], _p(beta), _p(other), _stream(theta))
+    return beta, other
+
+
+def vqls_terms_rhs(ansatz: AnsatzSpec, theta: torch.Tensor, strings: torch.Tensor, b: torch.Tensor,
+                   kind: str = "local", precision: str = "f64", exec_: str = "literal", out=None):
+    """Several right-hand sides b [R, 2^n] (real unit vectors) at the same
+    angles: (beta [B, L, L] once, other [R, B, ...]) complex128, block r as
+    vqls_terms with b_kind="vector", b=b[r]."""
+    theta = _cuda(theta, torch.float64, "theta")
+    if theta.dim() == 1:
+        theta = theta.unsqueeze(0)
+    strings = _cuda(strings, torch.int32, "strings")
+    b = _cuda(b, torch.float64, "b")
+    if b.dim() != 2 or b.shape[1] != 1 << ansatz.n:
+        raise ValueError(f"b must be [R, {1 << ansatz.n}], got {tuple(b.shape)}")
+    B, Lt, n, R = theta.shape[0], strings.shape[0], ansatz.n, b.shape[0]
+    _shape(theta, (B, ansatz.P), "theta")
+    _shape(strings, (Lt, 2), "strings")
+    oshape = (R, B, n, Lt, Lt) if kind == "local" else (R, B, Lt)
+    if out is None:
+        beta = torch.empty((B, Lt, Lt), dtype=torch.complex128, device=theta.device)
+        other = torch.empty(oshape, dtype=torch.complex128, device=theta.device)
+    else:
+        beta = _out(out[0], (B, Lt, Lt), torch.complex128, "beta")
+        other = _out(out[1], oshape, torch.complex128, "other")
+    a = ansatz.c()
+    L.call("dvq_vqls_terms_rhs", ctypes.byref(a), _p(theta), B, PRECISIONS[precision], _p(strings), Lt, R,
+           _p(b), KINDS[kind], EXECS[exec_], _p(beta), _p(other), _stream(theta))
     return beta, other
 
 
@@ -162,12 +222,16 @@ def vqls_cost(coeffs: torch.Tensor, n: int, kind: str, beta: torch.Tensor, other
     coeffs = _cuda(coeffs, torch.complex128, "coeffs")
     beta = _cuda(beta, torch.complex128, "beta")
     other = _cuda(other, torch.complex128, "other")
-    B = beta.shape[0]
+    B, Lt = beta.shape[0], coeffs.shape[0]
+    _shape(coeffs, (Lt,), "coeffs")
+    _shape(beta, (B, Lt, Lt), "beta")
+    _shape(other, (B, n, Lt, Lt) if kind == "local" else (B, Lt), "other")
     if out is None:
         C = torch.empty(B, dtype=torch.float64, device=beta.device)
         parts = torch.empty((B, 2), dtype=torch.complex128, device=beta.device)
     else:
-        C, parts = out
+        C = _out(out[0], (B,), torch.float64, "C")
+        parts = _out(out[1], (B, 2), torch.complex128, "parts")
     L.call("dvq_vqls_cost", _p(coeffs), coeffs.shape[0], n, KINDS[kind], _p(beta), _p(other), B,
            _p(C), _p(parts), _stream(beta))
     return C, parts
@@ -189,13 +253,18 @@ def vqls_grad_shift(ansatz: AnsatzSpec, theta: torch.Tensor, coeffs: torch.Tenso
     theta = _cuda(theta, torch.float64, "theta").reshape(-1)
     coeffs = _cuda(coeffs, torch.complex128, "coeffs")
     strings = _cuda(strings, torch.int32, "strings")
+    Lt = strings.shape[0]
+    _shape(theta, (ansatz.P,), "theta")
+    _shape(coeffs, (Lt,), "coeffs")
+    _shape(strings, (Lt, 2), "strings")
     if workspace is None:
-        workspace = ShiftWorkspace(ansatz, strings.shape[0], kind, theta.device)
+        workspace = ShiftWorkspace(ansatz, Lt, kind, theta.device)
     if out is None:
         C = torch.empty(1, dtype=torch.float64, device=theta.device)
         grad = torch.empty(ansatz.P, dtype=torch.float64, device=theta.device)
     else:
-        C, grad = out
+        C = _out(out[0], (1,), torch.float64, "C")
+        grad = _out(out[1], (ansatz.P,), torch.float64, "grad")
     bk, bt = _b_args(b_kind, b)
     a = ansatz.c()
     L.call("dvq_vqls_grad_shift", ctypes.byref(a), _p(theta), PRECISIONS[precision], _p(coeffs),
@@ -215,11 +284,15 @@ def vqls_grad_adjoint(ansatz: AnsatzSpec, theta: torch.Tensor, coeffs: torch.Ten
     strings = _cuda(strings, torch.int32, "strings")
     B = theta.shape[0]
     Lt = strings.shape[-2]
+    _shape(theta, (B, ansatz.P), "theta")
+    _shape(coeffs, (B, Lt) if per_row_system else (Lt,), "coeffs")
+    _shape(strings, (B, Lt, 2) if per_row_system else (Lt, 2), "strings")
     if out is None:
         C = torch.empty(B, dtype=torch.float64, device=theta.device)
         grad = torch.empty((B, ansatz.P), dtype=torch.float64, device=theta.device)
     else:
-        C, grad = out
+        C = _out(out[0], (B,), torch.float64, "C")
+        grad = _out(out[1], (B, ansatz.P), torch.float64, "grad")
     bk, bt = _b_args(b_kind, b)
     a = ansatz.c()
     L.call("dvq_vqls_grad_adjoint", ctypes.byref(a), _p(theta), B, PRECISIONS[precision],
@@ -246,9 +319,11 @@ class AdjointCost(torch.autograd.Function):
 
 
 def gd_step(theta: torch.Tensor, grad: torch.Tensor, lr: float) -> None:
-    """theta -= lr * grad, in place."""
-    if not theta.is_contiguous() or not grad.is_contiguous():
-        raise ValueError("gd_step needs contiguous tensors")
+    """theta -= lr * grad, in place (float64, contiguous, one size)."""
+    _out(theta, tuple(theta.shape), torch.float64, "theta")
+    _out(grad, tuple(grad.shape), torch.float64, "grad")
+    if theta.numel() != grad.numel():
+        raise ValueError(f"theta has {theta.numel()} elements, grad {grad.numel()}")
     L.call("dvq_gd_step", _p(theta), _p(grad), theta.numel(), float(lr), _stream(theta))
 
 
@@ -258,6 +333,8 @@ def fidelity(ansatz: AnsatzSpec, theta: torch.Tensor, target: torch.Tensor) -> t
     if theta.dim() == 1:
         theta = theta.unsqueeze(0)
     target = _cuda(target, torch.complex128, "target")
+    _shape(theta, (theta.shape[0], ansatz.P), "theta")
+    _shape(target, (1 << ansatz.n,), "target")
     F = torch.empty(theta.shape[0], dtype=torch.float64, device=theta.device)
     a = ansatz.c()
     L.call("dvq_fidelity", ctypes.byref(a), _p(theta), theta.shape[0], _p(target), _p(F), _stream(theta))
@@ -279,12 +356,16 @@ def mlp_forward(shape: L.MlpShape, params: torch.Tensor, X: torch.Tensor, out=No
     params = _cuda(params, torch.float32, "params")
     X = _cuda(X, torch.float32, "X")
     B = X.shape[0]
+    _shape(params, (mlp_param_count(shape),), "params")
+    _shape(X, (B, shape.d_in), "X")
     if out is None:
         H1 = torch.empty((B, shape.hidden), dtype=torch.float32, device=X.device)
         H2 = torch.empty_like(H1)
         Y = torch.empty((B, shape.d_out), dtype=torch.float32, device=X.device)
     else:
-        Y, H1, H2 = out
+        Y = _out(out[0], (B, shape.d_out), torch.float32, "Y")
+        H1 = _out(out[1], (B, shape.hidden), torch.float32, "H1")
+        H2 = _out(out[2], (B, shape.hidden), torch.float32, "H2")
     L.call("dvq_mlp_forward", ctypes.byref(shape), _p(params), _p(X), B, _p(H1), _p(H2), _p(Y), _stream(X))
     return Y, H1, H2
 
@@ -293,23 +374,33 @@ def mlp_loss_grad(Y: torch.Tensor, T: torch.Tensor, out=None):
     """(dY float32, loss float64 [1]) of mean(1 - cos(Y - T))."""
     Y = _cuda(Y, torch.float32, "Y")
     T = _cuda(T, torch.float32, "T")
+    _shape(T, tuple(Y.shape), "T")
     if out is None:
         dY = torch.empty_like(Y)
         loss = torch.empty(1, dtype=torch.float64, device=Y.device)
     else:
-        dY, loss = out
+        dY = _out(out[0], tuple(Y.shape), torch.float32, "dY")
+        loss = _out(out[1], (1,), torch.float64, "loss")
     L.call("dvq_mlp_loss_grad", _p(Y), _p(T), Y.numel(), _p(dY), _p(loss), _stream(Y))
     return dY, loss
 
 
 def mlp_backward(shape: L.MlpShape, params, X, H1, H2, dY, workspace=None, out=None):
     """Parameter gradients, packed like params."""
+    params = _cuda(params, torch.float32, "params")
+    X, H1, H2, dY = (_cuda(t, torch.float32, nm) for t, nm in ((X, "X"), (H1, "H1"), (H2, "H2"), (dY, "dY")))
     B = X.shape[0]
+    P = mlp_param_count(shape)
+    _shape(params, (P,), "params")
+    _shape(X, (B, shape.d_in), "X")
+    _shape(H1, (B, shape.hidden), "H1")
+    _shape(H2, (B, shape.hidden), "H2")
+    _shape(dY, (B, shape.d_out), "dY")
     lib = L.load()
     if workspace is None:
         workspace = torch.empty(lib.dvq_mlp_workspace_bytes(ctypes.byref(shape), B), dtype=torch.uint8,
                                 device=X.device)
-    dparams = torch.empty_like(params) if out is None else out
+    dparams = torch.empty_like(params) if out is None else _out(out, (P,), torch.float32, "out")
     L.call("dvq_mlp_backward", ctypes.byref(shape), _p(params), _p(X), _p(H1), _p(H2), _p(dY), B,
            _p(dparams), _p(workspace), workspace.numel(), _stream(X))
     return dparams
@@ -317,5 +408,9 @@ def mlp_backward(shape: L.MlpShape, params, X, H1, H2, dY, workspace=None, out=N
 
 def adamw_step(params, grads, m, v, t: int, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
                eps: float = 1e-8, weight_decay: float = 0.0) -> None:
+    """In place on params, m, v (float32, contiguous, one size)."""
+    for t, nm in ((params, "params"), (m, "m"), (v, "v")):
+        _out(t, tuple(params.shape), torch.float32, nm)
+    grads = _shape(_cuda(grads, torch.float32, "grads"), tuple(params.shape), "grads")
     L.call("dvq_adamw_step", _p(params), _p(grads), _p(m), _p(v), params.numel(), int(t), float(lr),
            float(beta1), float(beta2), float(eps), float(weight_decay), _stream(params))

@@ -22,8 +22,20 @@ struct TermsArgs {
     dvq_c128* beta;
     dvq_c128* other;
     int n, layers, ent, L, kind, bkind, B;
-    int64_t per_row, total;
+    int64_t c0;       // first circuit (in decode_term order) of each row's range
+    int64_t per_row;  // circuits per row in this launch: c0 .. c0 + per_row - 1
+    int64_t total;    // per_row * B
 };
+
+// The same launch restricted to circuits first .. first + count - 1 of each
+// row (first and count even: whole Re/Im pairs).
+inline TermsArgs sub_range(const TermsArgs& g, int64_t first, int64_t count) {
+    TermsArgs r = g;
+    r.c0 = first;
+    r.per_row = count;
+    r.total = count * g.B;
+    return r;
+}
 
 // Circuit c of one theta row.  Order: consecutive pairs (Re, Im) of one term;
 // local: terms t = jj*L^2 + l*L + m with jj = 0 for beta and jj = j+1 for

@@ -19,7 +19,7 @@ __global__ void __launch_bounds__(256) k_terms_generic(TermsArgs g) {
     const int64_t gid = (int64_t)blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
     if (gid >= g.total) return;
     const int64_t row = gid / g.per_row;
-    const Term t = decode_term(gid - row * g.per_row, g.L, n, g.kind);
+    const Term t = decode_term(g.c0 + gid - row * g.per_row, g.L, n, g.kind);
 
     lds_trig<T>(trig, g.theta + row * P, P);
     for (int i = threadIdx.x; i < na; i += blockDim.x) a[i] = {(T)(i == 0 ? 1 : 0), (T)0};
@@ -87,13 +87,31 @@ static dvq_status launch_generic(const TermsArgs& g, hipStream_t s) {
     return DVQ_OK;
 }
 
+static dvq_status launch_generic_p(const TermsArgs& g, int precision, hipStream_t s) {
+    return precision == DVQ_F32 ? launch_generic<float>(g, s) : launch_generic<double>(g, s);
+}
+
+// Global cost: the beta circuits (the first 2 L^2 of a row) go to the
+// register-resident kernels where the shape has them, the gamma circuits
+// (controlled V(theta), 2 L per row) to the generic kernel.
 dvq_status launch_terms(const TermsArgs& g, int precision, int exec, hipStream_t s) {
     if (exec == DVQ_EXEC_LITERAL || exec == DVQ_EXEC_SHARED) {
-        dvq_status st = exec == DVQ_EXEC_LITERAL ? launch_terms_fast(g, precision, s)
-                                                 : launch_terms_shared(g, precision, s);
-        if (st != DVQ_EUNSUPPORTED) return st;
+        auto fast = [&](const TermsArgs& a) {
+            return exec == DVQ_EXEC_LITERAL ? launch_terms_fast(a, precision, s) : launch_terms_shared(a, precision, s);
+        };
+        const int64_t nbeta = 2 * (int64_t)g.L * g.L, end = g.c0 + g.per_row;
+        if (g.kind == DVQ_COST_GLOBAL && g.c0 < nbeta) {
+            const int64_t bend = end < nbeta ? end : nbeta;
+            dvq_status st = fast(sub_range(g, g.c0, bend - g.c0));
+            if (st == DVQ_OK)
+                return end > nbeta ? launch_generic_p(sub_range(g, nbeta, end - nbeta), precision, s) : DVQ_OK;
+            if (st != DVQ_EUNSUPPORTED) return st;
+        } else if (g.kind == DVQ_COST_LOCAL) {
+            dvq_status st = fast(g);
+            if (st != DVQ_EUNSUPPORTED) return st;
+        }
     }
-    return precision == DVQ_F32 ? launch_generic<float>(g, s) : launch_generic<double>(g, s);
+    return launch_generic_p(g, precision, s);
 }
 
 dvq_status check_ansatz(const dvq_ansatz* an, int max_n) {
@@ -132,6 +150,7 @@ dvq_status make_terms_args(TermsArgs& g, const dvq_ansatz* an, const double* the
     g.L = L;
     g.kind = cost_kind;
     g.bkind = b_kind;
+    g.c0 = 0;
     g.per_row = per_row;
     g.total = per_row * B;
     g.B = B;
@@ -154,4 +173,31 @@ extern "C" dvq_status dvq_vqls_terms(const dvq_ansatz* ansatz, const double* the
     DVQ_REQUIRE(exec == DVQ_EXEC_LITERAL || exec == DVQ_EXEC_GENERIC || exec == DVQ_EXEC_SHARED,
                 "unknown exec %d", exec);
     return launch_terms(g, precision, exec, stream_of(stream));
+}
+
+extern "C" dvq_status dvq_vqls_terms_rhs(const dvq_ansatz* ansatz, const double* theta, int32_t B,
+                                         int32_t precision, const dvq_pauli* strings, int32_t L, int32_t R,
+                                         const double* b, int32_t cost_kind, int32_t exec, dvq_c128* beta,
+                                         dvq_c128* other, dvq_stream stream) {
+    DVQ_REQUIRE(R >= 1 && R <= 65536, "R=%d outside 1..65536", R);
+    DVQ_REQUIRE(b != nullptr, "b is NULL");
+    TermsArgs g;
+    dvq_status st = make_terms_args(g, ansatz, theta, B, precision, strings, L, DVQ_B_VECTOR, b, cost_kind,
+                                    beta, other);
+    if (st != DVQ_OK) return st;
+    DVQ_REQUIRE(exec == DVQ_EXEC_LITERAL || exec == DVQ_EXEC_GENERIC || exec == DVQ_EXEC_SHARED,
+                "unknown exec %d", exec);
+    const hipStream_t s = stream_of(stream);
+    const int64_t N = int64_t(1) << g.n, nbeta = 2 * (int64_t)L * L;
+    const int64_t other_row = cost_kind == DVQ_COST_LOCAL ? (int64_t)g.n * L * L : (int64_t)L;
+    // beta does not involve b: once
+    if ((st = launch_terms(sub_range(g, 0, nbeta), precision, exec, s)) != DVQ_OK) return st;
+    // the b-dependent circuits, once per right-hand side
+    for (int r = 0; r < R; ++r) {
+        TermsArgs gr = sub_range(g, nbeta, g.per_row - nbeta);
+        gr.b = b + r * N;
+        gr.other = other + (int64_t)r * B * other_row;
+        if ((st = launch_terms(gr, precision, exec, s)) != DVQ_OK) return st;
+    }
+    return DVQ_OK;
 }

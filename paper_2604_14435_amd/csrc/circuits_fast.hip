@@ -263,7 +263,7 @@ __global__ void __launch_bounds__(64) k_terms_fast(TermsArgs g) {
     const int64_t gid = (int64_t)blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
     if (gid >= g.total) return;
     const int64_t row = gid / g.per_row;
-    const Term t = decode_term(gid - row * g.per_row, g.L, NQ, g.kind);
+    const Term t = decode_term(g.c0 + gid - row * g.per_row, g.L, NQ, g.kind);
 
     simulate_prefix<T, NQ, ENT>(g.theta + row * P, g.layers, S, trig, lane);
     T z;
@@ -300,7 +300,7 @@ __global__ void __launch_bounds__(64) k_terms_shared(TermsArgs g, int64_t chunk,
 
     simulate_prefix<T, NQ, ENT>(g.theta + row * P, g.layers, S, trig, lane);
     for (int64_t c = c0; c < c1; c += 2) {
-        const Term t = decode_term(c, g.L, NQ, g.kind);
+        const Term t = decode_term(g.c0 + c, g.L, NQ, g.kind);
         T zr, zi;
         if (BVEC && t.type == kDelta) {
             // reads half 0, uses half 1 as scratch
@@ -374,8 +374,11 @@ static dvq_status launch_shared(const TermsArgs& g, hipStream_t s) {
               : launch_shared_ent<T, NQ, DVQ_ENT_CNOT_LADDER, false>(g, s);
 }
 
+// Local cost, or a global-cost range holding beta circuits only (the gamma
+// circuits control V(theta), which these kernels do not).
 static bool fast_shape(const TermsArgs& g) {
-    return g.kind == DVQ_COST_LOCAL && g.n * g.layers <= 1024 && (g.bkind == DVQ_B_PLUS || g.b != nullptr);
+    const bool kind_ok = g.kind == DVQ_COST_LOCAL || g.c0 + g.per_row <= 2 * (int64_t)g.L * g.L;
+    return kind_ok && g.n * g.layers <= 1024 && (g.bkind == DVQ_B_PLUS || g.b != nullptr);
 }
 
 dvq_status launch_terms_fast(const TermsArgs& g, int precision, hipStream_t s) {

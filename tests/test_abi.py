@@ -68,6 +68,19 @@ def test_terms_rejects_null_and_sizes():
     assert b"exec" in lib.dvq_last_error()
 
 
+def test_terms_rhs_rejects_bad_input():
+    lib = L.load()
+    a = L.Ansatz(3, 2, 0)
+    d = ctypes.c_void_p(16)
+    f = lib.dvq_vqls_terms_rhs
+    assert f(ctypes.byref(a), d, 1, 0, d, 8, 0, d, 0, 0, d, d, None) == L.DVQ_EINVAL  # R < 1
+    assert f(ctypes.byref(a), d, 1, 0, d, 8, 65537, d, 0, 0, d, d, None) == L.DVQ_EINVAL  # R too large
+    assert f(ctypes.byref(a), d, 1, 0, d, 8, 2, None, 0, 0, d, d, None) == L.DVQ_EINVAL  # no b
+    assert f(ctypes.byref(a), d, 1, 0, d, 8, 2, d, 5, 0, d, d, None) == L.DVQ_EINVAL  # cost kind
+    assert f(ctypes.byref(a), d, 1, 0, d, 8, 2, d, 0, 9, d, d, None) == L.DVQ_EINVAL  # exec
+    assert b"exec" in lib.dvq_last_error()
+
+
 def test_decompose_rejects_bad_input():
     lib = L.load()
     lout = ctypes.c_int64(-1)
@@ -109,3 +122,23 @@ def test_grad_entry_points_reject_bad_input():
     assert lib.dvq_vqls_grad_shift(ctypes.byref(a), d, 0, d, d, 8, 0, None, 0, d, d, d, need - 1, None) == L.DVQ_ECAPACITY
     assert lib.dvq_gd_step(None, d, 4, 0.1, None) == L.DVQ_EINVAL
     assert lib.dvq_gd_step(d, d, -1, 0.1, None) == L.DVQ_EINVAL
+
+
+def test_binding_checks_shapes_before_any_launch():
+    """The kernels index buffers by the sizes they are given: the binding
+    rejects mismatched inputs and outputs before calling the library (the
+    tensors are never touched, so CPU tensors stand in: the dtype/device
+    check comes first and is what fires for them)."""
+    torch = pytest.importorskip("torch")
+    from paper_2604_14435_amd import api
+
+    an = api.AnsatzSpec(3, 2, "cz")
+    with pytest.raises(TypeError):
+        api.vqls_terms(an, torch.zeros(1, 6, dtype=torch.float64), torch.zeros(2, 2, dtype=torch.int32))
+    with pytest.raises(ValueError):
+        api._shape(torch.zeros(1, 5), (1, 6), "theta")
+    with pytest.raises(TypeError):
+        api._out(torch.zeros(1, 6, dtype=torch.float64), (1, 6), torch.float64, "out")
+    with pytest.raises(ValueError):
+        api._square(torch.zeros(6, 6))
+    api._square(torch.zeros(8, 8))

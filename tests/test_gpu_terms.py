@@ -201,3 +201,60 @@ def test_prefix_shared_mode(n, layers, precision, ent, bk):
             j = int(rng.integers(0, n))
             want = qc.delta_term(th[r], n, layers, ent, sl, sm, j, b_kind=bk, b=bvec)
             assert abs(ds[r, j, l, m] - want) < tol
+
+
+@pytest.mark.parametrize("n,layers,precision,kind,exec_", [
+    (10, 4, "f32", "local", "literal"), (10, 3, "f64", "local", "shared"), (10, 2, "f32", "global", "literal"),
+    (4, 2, "f64", "local", "generic"), (4, 3, "f64", "global", "literal")])
+def test_terms_rhs_equal_separate_calls(n, layers, precision, kind, exec_):
+    """Several right-hand sides at the same angles: beta once, the
+    b-dependent terms per b, equal bit for bit to one vqls_terms call per b
+    (B = 2 rows, R = 3, ragged L = 6); sampled terms against the oracle."""
+    rng = np.random.default_rng(100 + n + layers)
+    N = 1 << n
+    strings = rng.integers(0, N, size=(6, 2)).astype(np.int32)
+    strings[0] = (0, 0)
+    th = rng.uniform(0, 2 * math.pi, size=(2, n * layers))
+    an = api.AnsatzSpec(n, layers, "cz")
+    bs = np.stack([random_unit_vector(N, seed=40 + r) for r in range(3)])
+    beta, other = api.vqls_terms_rhs(an, _gpu(th), _gpu(strings), _gpu(bs), kind, precision, exec_=exec_)
+    assert other.shape[0] == 3
+    for r in range(3):
+        b1, o1 = api.vqls_terms(an, _gpu(th), _gpu(strings), kind, precision, b_kind="vector", b=_gpu(bs[r]),
+                                exec_=exec_)
+        assert torch.equal(beta, b1)
+        assert torch.equal(other[r], o1)
+    tol = TOL[precision]
+    o = other.cpu().numpy()
+    for r in range(3):
+        l, m = (int(v) for v in rng.integers(0, 6, 2))
+        sl, sm = (int(strings[l, 0]), int(strings[l, 1])), (int(strings[m, 0]), int(strings[m, 1]))
+        if kind == "local":
+            j = int(rng.integers(0, n))
+            want = qc.delta_term(th[1], n, layers, "cz", sl, sm, j, b_kind="vector", b=bs[r])
+            assert abs(o[r, 1, j, l, m] - want) < tol
+        else:
+            assert abs(o[r, 1, l] - qc.gamma_term(th[1], n, layers, "cz", sl, "vector", bs[r])) < tol
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("exec_", ["literal", "shared"])
+def test_global_cost_split_launch(precision, exec_):
+    """Global cost at n = 10: the beta circuits on the register-resident
+    kernels, gamma on the generic kernel; every term against the generic
+    kernel alone, sampled terms against the oracle."""
+    n, layers = 10, 2
+    rng = np.random.default_rng(5)
+    strings = rng.integers(0, 1 << n, size=(5, 2)).astype(np.int32)
+    th = rng.uniform(0, 2 * math.pi, size=(2, n * layers))
+    an = api.AnsatzSpec(n, layers, "cnot")
+    beta, gamma = api.vqls_terms(an, _gpu(th), _gpu(strings), "global", precision, exec_=exec_)
+    gb, gg = api.vqls_terms(an, _gpu(th), _gpu(strings), "global", precision, exec_="generic")
+    tol = TOL[precision]
+    assert torch.max(torch.abs(beta - gb)).item() < 2 * tol
+    assert torch.equal(gamma, gg)  # the same kernel computes gamma on both routes
+    beta = beta.cpu().numpy()
+    for _ in range(4):
+        l, m = (int(v) for v in rng.integers(0, 5, 2))
+        sl, sm = (int(strings[l, 0]), int(strings[l, 1])), (int(strings[m, 0]), int(strings[m, 1]))
+        assert abs(beta[1, l, m] - qc.beta_term(th[1], n, layers, "cnot", sl, sm)) < tol
