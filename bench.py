@@ -741,6 +741,51 @@ def adjoint_workload(api, dev, reps=5):
                                   "fp32_circuits": abs(C.item() - Cs.item())}}
 
 
+def multi_rhs(api, dev, coeffs, strings, R=8, reps=5):
+    """Several right-hand sides with the same A and angles (n = 10, L = 64,
+    4 layers RY + CZ, theta from seed 0, R seeded real unit b): beta's
+    2 L^2 circuits once and the b-dependent circuits per b
+    (dvq_vqls_terms_rhs), against R separate evaluations, complex64 states,
+    local and global cost; the costs from both routes compared."""
+    import numpy as np
+    import torch
+
+    from workloads import random_unit_vector, theta_uniform
+
+    n, layers = N_QUBITS, LAYERS
+    an = api.AnsatzSpec(n, layers, "cz")
+    L = int(coeffs.shape[0])
+    th = torch.from_numpy(theta_uniform(an.P, seed=0)).to(dev)
+    bs = torch.from_numpy(np.stack([random_unit_vector(1 << n, seed=200 + r) for r in range(R)])).to(dev)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    out = {"R": R, "b": f"{R} real unit vectors, seeds 200..{199 + R}"}
+    for kind in ("local", "global"):
+        per_row = int(api.circuit_count(n, L, kind))
+        t_sep = timed(lambda: [api.vqls_terms(an, th, strings, kind, "f32", b_kind="vector", b=bs[r])
+                               for r in range(R)])
+        t_rhs = timed(lambda: api.vqls_terms_rhs(an, th, strings, bs, kind, "f32"))
+        beta, other = api.vqls_terms_rhs(an, th, strings, bs, kind, "f32")
+        diff = 0.0
+        for r in range(R):
+            b1, o1 = api.vqls_terms(an, th, strings, kind, "f32", b_kind="vector", b=bs[r])
+            c_rhs = api.vqls_cost(coeffs, n, kind, beta, other[r])[0].item()
+            c_sep = api.vqls_cost(coeffs, n, kind, b1, o1)[0].item()
+            diff = max(diff, abs(c_rhs - c_sep))
+        out[kind] = {"circuits_separate": R * per_row, "circuits_shared_beta": 2 * L * L + R * (per_row - 2 * L * L),
+                     "ms_separate": round(t_sep * 1e3, 3), "ms_shared_beta": round(t_rhs * 1e3, 3),
+                     "speedup": round(t_sep / t_rhs, 2), "max_cost_difference": diff}
+    return out
+
+
 def pruning_sweep(api, dev):
     """Accuracy of the pruned operator (Section III-B): n = 10,
     tridiag(-1/3, 1, -1/3), the paper's tau list.  Decomposition, selection
@@ -1009,6 +1054,8 @@ def main() -> int:
     out["pruning_sweep"] = pruning_sweep(api, dev)
     out["adjoint_L128"] = adjoint_workload(api, dev)
     progress("L=128 adjoint workload done")
+    out["multi_rhs"] = multi_rhs(api, dev, coeffs, strings)
+    progress("several right-hand sides done")
     if not args.no_heleshaw:
         out["heleshaw"] = heleshaw_run(api, dev)
         progress("Hele-Shaw-like system done")

@@ -285,6 +285,9 @@ def vqls_grad_adjoint(ansatz: AnsatzSpec, theta: torch.Tensor, coeffs: torch.Ten
     B = theta.shape[0]
     Lt = strings.shape[-2]
     _shape(theta, (B, ansatz.P), "theta")
+    if not per_row_system:  # one system for every row: [L] or [1, L]
+        coeffs = coeffs.reshape(-1) if coeffs.dim() == 2 and coeffs.shape[0] == 1 else coeffs
+        strings = strings.reshape(-1, 2) if strings.dim() == 3 and strings.shape[0] == 1 else strings
     _shape(coeffs, (B, Lt) if per_row_system else (Lt,), "coeffs")
     _shape(strings, (B, Lt, 2) if per_row_system else (Lt, 2), "strings")
     if out is None:
@@ -409,8 +412,8 @@ def mlp_backward(shape: L.MlpShape, params, X, H1, H2, dY, workspace=None, out=N
 def adamw_step(params, grads, m, v, t: int, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
                eps: float = 1e-8, weight_decay: float = 0.0) -> None:
     """In place on params, m, v (float32, contiguous, one size)."""
-    for t, nm in ((params, "params"), (m, "m"), (v, "v")):
-        _out(t, tuple(params.shape), torch.float32, nm)
+    for buf, nm in ((params, "params"), (m, "m"), (v, "v")):
+        _out(buf, tuple(params.shape), torch.float32, nm)
     grads = _shape(_cuda(grads, torch.float32, "grads"), tuple(params.shape), "grads")
     L.call("dvq_adamw_step", _p(params), _p(grads), _p(m), _p(v), params.numel(), int(t), float(lr),
            float(beta1), float(beta2), float(eps), float(weight_decay), _stream(params))
