@@ -51,26 +51,38 @@ namespace dvq {
 // the pending ladder (sign or permutation) applied.  `trig` receives the
 // rotation parameters phi = theta/2 reduced to [-pi/2, pi/2]: tan(phi/2),
 // sin(phi).
-template <typename T, int NQ, int ENT>
-__device__ __forceinline__ void simulate_prefix(const double* __restrict__ theta, int layers,
-                                                cplx<T>* S, T* trig, int lane) {
+// The prefix in registers: |0> with H on the ancilla (1/sqrt(2) at g = 0
+// and g = 2^n, layout LO), then V(theta), swapping layouts through the LDS
+// image S (interleaved cplx<T>* or planar T*).  Ends as forward_layers /
+// forward_layers_ladder leave it.
+template <typename T, int NQ, int ENT, typename Buf>
+__device__ __forceinline__ void prefix_registers(const double* __restrict__ theta, int layers, Buf S, T* trig,
+                                                 int lane, T* re, T* im) {
     constexpr int R = Lay<NQ, false>::R;
     rotation_table<T>(theta, NQ * layers, trig, lane);
-    // |0> with H on the ancilla: 1/sqrt(2) at g = 0 and g = 2^n (layout LO).
-    T re[R], im[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         re[r] = (r == 0 && (lane & 31) == 0) ? (T)0.70710678118654752440 : (T)0;
         im[r] = (T)0;
     }
-    if constexpr (ENT == DVQ_ENT_CZ_LADDER) {
+    if constexpr (ENT == DVQ_ENT_CZ_LADDER)
         forward_layers<T, NQ>(re, im, S, trig, layers, lane);
+    else
+        forward_layers_ladder<T, NQ>(re, im, S, trig, layers, lane);
+}
+
+template <typename T, int NQ, int ENT>
+__device__ __forceinline__ void simulate_prefix(const double* __restrict__ theta, int layers,
+                                                cplx<T>* S, T* trig, int lane) {
+    constexpr int R = Lay<NQ, false>::R;
+    T re[R], im[R];
+    prefix_registers<T, NQ, ENT>(theta, layers, S, trig, lane, re, im);
+    if constexpr (ENT == DVQ_ENT_CZ_LADDER) {
         if (layers & 1)
             store_state<T, NQ, true>(re, im, S, lane, 1);
         else
             store_state<T, NQ, false>(re, im, S, lane, 0);
     } else {
-        forward_layers_ladder<T, NQ>(re, im, S, trig, layers, lane);
         if (layers & 1)
             store_state_ladder<T, NQ, true>(re, im, S, lane);
         else
@@ -179,6 +191,54 @@ __device__ __forceinline__ void measure_suffix_pair(const cplx<T>* S, SignedPerm
     zim = wave_sum(zi);
 }
 
+// measure_suffix on a planar image, from the registers prefix_registers
+// left: the final state goes to LDS one component at a time (with the
+// pending ladder sign or frame) and each lane gathers, per component, its
+// ancilla = 0 amplitudes and the permuted ancilla = 1 amplitudes; then the
+// same S^dagger / H / <Z_anc> as measure_suffix.
+template <typename T, int NQ, int ENT>
+__device__ __forceinline__ T measure_planar(T* re, T* im, T* P, SignedPerm sp, int imag, int layers, int lane) {
+    constexpr int N = 1 << NQ, KPL = N / 64;
+    const T r2 = (T)0.70710678118654752440;
+    const bool odd = layers & 1;
+    if constexpr (ENT != DVQ_ENT_CZ_LADDER)
+        if (odd) relayout_ladder<T, NQ, true>(re, im, P, lane);  // HI ladder frame -> LO true frame
+    const SuffixLane sl = suffix_lane(sp, lane);
+    T a0r[KPL], a0i[KPL], gr[KPL], gi[KPL];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const T* x = c ? im : re;
+        if constexpr (ENT == DVQ_ENT_CZ_LADDER) {
+            if (odd)
+                store_plane<T, NQ, true>(x, P, lane, 1);
+            else
+                store_plane<T, NQ, false>(x, P, lane, 0);
+        } else {
+            if (odd)
+                store_plane_ladder_lo<T, NQ, false>(x, P, lane);
+            else
+                store_plane_ladder_lo<T, NQ, true>(x, P, lane);
+        }
+        T* a0 = c ? a0i : a0r;
+        T* gx = c ? gi : gr;
+#pragma unroll
+        for (int i = 0; i < KPL; ++i) {
+            a0[i] = P[pad_slot(lane + 64 * i)];
+            gx[i] = P[suffix_slot(sl, N, i)];
+        }
+        __syncthreads();  // every lane has read this component
+    }
+    T z = 0;
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+        const cplx<T> a1 = mul_ipow(cplx<T>{gr[i], gi[i]}, suffix_pow(sl, i) + (imag ? 3 : 0));
+        const T b0r = (a0r[i] + a1.re) * r2, b0i = (a0i[i] + a1.im) * r2;
+        const T b1r = (a0r[i] - a1.re) * r2, b1i = (a0i[i] - a1.im) * r2;
+        z += (b0r * b0r + b0i * b0i) - (b1r * b1r + b1i * b1i);
+    }
+    return wave_sum(z);
+}
+
 // Phase power of one Pauli string: (P v)[k] = i^p (-1)^{z.k} v[k ^ x] with
 // p = |x&z| + 2 (|x&z| mod 2) (P = i^{|x&z|} X^x Z^z).
 __device__ __forceinline__ int string_pow(const dvq_pauli ps) {
@@ -250,13 +310,18 @@ __device__ __forceinline__ void measure_suffix_bvec(cplx<T>* S, dvq_pauli pl, dv
 // (No occupancy bound: at n = 10 in float32 the kernel takes 144 VGPRs,
 // three wavefronts per SIMD; bounding it to 128 for four spills to scratch
 // and measured 4 % slower.)
+// Planar LDS image for float64 states with b = |+>: two wavefronts per
+// SIMD instead of one (the interleaved image would take 33 KB per wave).
+template <typename T, bool BVEC>
+__host__ __device__ constexpr bool planar_lds() {
+    return sizeof(T) == 8 && !BVEC;
+}
+
 template <typename T, int NQ, int ENT, bool BVEC>
 __global__ void __launch_bounds__(64) k_terms_fast(TermsArgs g) {
     constexpr int N = 1 << NQ;
     constexpr int NSLOT = 2 * N + (2 * N) / 32;
     extern __shared__ __align__(16) unsigned char smem[];
-    cplx<T>* S = reinterpret_cast<cplx<T>*>(smem);
-    T* trig = reinterpret_cast<T*>(S + NSLOT);
     const int lane = threadIdx.x;
     const int P = NQ * g.layers;
 
@@ -265,6 +330,19 @@ __global__ void __launch_bounds__(64) k_terms_fast(TermsArgs g) {
     const int64_t row = gid / g.per_row;
     const Term t = decode_term(g.c0 + gid - row * g.per_row, g.L, NQ, g.kind);
 
+    if constexpr (planar_lds<T, BVEC>()) {
+        T* Pl = reinterpret_cast<T*>(smem);
+        T* trig = Pl + NSLOT;
+        constexpr int R = Lay<NQ, false>::R;
+        T re[R], im[R];
+        prefix_registers<T, NQ, ENT>(g.theta + row * P, g.layers, Pl, trig, lane, re, im);
+        const SignedPerm sp = suffix_perm(g.strings[t.l], g.strings[t.m], t.type, t.j);
+        const T z = measure_planar<T, NQ, ENT>(re, im, Pl, sp, t.part, g.layers, lane);
+        if (lane == 0) store_term(g, row, t, (double)z);
+        return;
+    }
+    cplx<T>* S = reinterpret_cast<cplx<T>*>(smem);
+    T* trig = reinterpret_cast<T*>(S + NSLOT);
     simulate_prefix<T, NQ, ENT>(g.theta + row * P, g.layers, S, trig, lane);
     T z;
     if (BVEC && t.type == kDelta) {
@@ -319,14 +397,15 @@ __global__ void __launch_bounds__(64) k_terms_shared(TermsArgs g, int64_t chunk,
 }
 
 template <typename T, int NQ>
-static size_t fast_lds_bytes(int layers) {
+static size_t fast_lds_bytes(int layers, bool planar = false) {
     constexpr int N = 1 << NQ;
-    return (size_t)(2 * N + (2 * N) / 32) * sizeof(cplx<T>) + (size_t)2 * NQ * layers * sizeof(T);
+    return (size_t)(2 * N + (2 * N) / 32) * (planar ? sizeof(T) : sizeof(cplx<T>)) +
+           (size_t)2 * NQ * layers * sizeof(T);
 }
 
 template <typename T, int NQ, int ENT, bool BVEC>
 static dvq_status launch_fast_ent(const TermsArgs& g, hipStream_t s) {
-    const size_t lds = fast_lds_bytes<T, NQ>(g.layers);
+    const size_t lds = fast_lds_bytes<T, NQ>(g.layers, planar_lds<T, BVEC>());
     DVQ_TRY_HIP(allow_lds((const void*)k_terms_fast<T, NQ, ENT, BVEC>, lds));
     hipLaunchKernelGGL((k_terms_fast<T, NQ, ENT, BVEC>), grid_for(g.total), dim3(64), lds, s, g);
     DVQ_CHECK_LAUNCH("k_terms_fast");

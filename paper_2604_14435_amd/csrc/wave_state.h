@@ -142,6 +142,27 @@ __device__ __forceinline__ void relayout(T* re, T* im, cplx<T>* S, int lane) {
     __syncthreads();
 }
 
+// Planar LDS image: one component at a time in 2^(NQ+1) (+ pad) values.
+// A float64 state takes 16 B per amplitude, so the interleaved image (33 KB
+// at NQ = 10) holds a CU to four wavefronts; the planar one (17 KB) moves
+// the real parts and then the imaginary parts through half the space.
+template <typename T, int NQ, bool FROM_HI>
+__device__ __forceinline__ void relayout_plane(T* x, T* P, int lane) {
+    constexpr int R = Lay<NQ, FROM_HI>::R;
+#pragma unroll
+    for (int r = 0; r < R; ++r) P[pad_slot(Lay<NQ, FROM_HI>::g(lane, r))] = x[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = P[pad_slot(Lay<NQ, !FROM_HI>::g(lane, r))];
+    __syncthreads();
+}
+
+template <typename T, int NQ, bool FROM_HI>
+__device__ __forceinline__ void relayout(T* re, T* im, T* P, int lane) {
+    relayout_plane<T, NQ, FROM_HI>(re, P, lane);
+    relayout_plane<T, NQ, FROM_HI>(im, P, lane);
+}
+
 // ---------------------------------------------------------------- CNOT ladder
 
 // pi on the NQ system bits of g (bit NQ, the half, is kept); linear over
@@ -278,6 +299,33 @@ __device__ __forceinline__ void relayout_ladder(T* re, T* im, cplx<T>* S, int la
     __syncthreads();
 }
 
+// The same swap on a planar image, one component.
+template <typename T, int NQ, bool FROM_HI>
+__device__ __forceinline__ void relayout_ladder_plane(T* x, T* P, int lane) {
+    using From = Lay<NQ, FROM_HI>;
+    using To = Lay<NQ, !FROM_HI>;
+    constexpr int R = From::R;
+    constexpr int SPLIT = FROM_HI ? To::RB : 5;
+#pragma unroll
+    for (int r = 0; r < R; ++r) P[pad_slot(From::g(lane, r))] = x[r];
+    __syncthreads();
+    const int ub = ladder_unperm<NQ>(To::glane(lane));
+    const int base0 = pad_slot(ub), base1 = pad_slot(ub ^ (1 << SPLIT));
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int u = ladder_unperm<NQ>(To::greg(r));
+        const int off = u & ~(1 << SPLIT);
+        x[r] = P[((u >> SPLIT) & 1 ? base1 : base0) + off + (off >> 5)];
+    }
+    __syncthreads();
+}
+
+template <typename T, int NQ, bool FROM_HI>
+__device__ __forceinline__ void relayout_ladder(T* re, T* im, T* P, int lane) {
+    relayout_ladder_plane<T, NQ, FROM_HI>(re, P, lane);
+    relayout_ladder_plane<T, NQ, FROM_HI>(im, P, lane);
+}
+
 // Write the registers (ladder frame) to LDS in natural order: slot pi(k).
 // In LO, pi of the register part is prefix(r) in bits 0..RB-1 and the
 // parity of r in every higher bit, so again two bases and an offset; HI
@@ -303,15 +351,37 @@ __device__ __forceinline__ void store_state_ladder(T* re, T* im, cplx<T>* S, int
     __syncthreads();
 }
 
+// One component of the registers to a planar image in natural order:
+// layout LO, ladder frame (slot pi(k)), or true frame (after a ladder swap
+// from HI).
+template <typename T, int NQ, bool FRAME>
+__device__ __forceinline__ void store_plane_ladder_lo(const T* x, T* P, int lane) {
+    using Lo = Lay<NQ, false>;
+    constexpr int R = Lo::R, RB = Lo::RB;
+    constexpr int HM = ((1 << NQ) - 1) & ~((1 << RB) - 1);
+    if constexpr (!FRAME) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) P[pad_slot(Lo::g(lane, r))] = x[r];
+    } else {
+        const int pl = ladder_perm<NQ>(Lo::glane(lane));
+        const int base0 = pad_slot(pl), base1 = pad_slot(pl ^ HM);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int off = ladder_perm<NQ>(r) & ((1 << RB) - 1);
+            P[(odd_bits(r) ? base1 : base0) + off + (off >> 5)] = x[r];
+        }
+    }
+    __syncthreads();
+}
+
 // Forward pass of the RY + CNOT-ladder ansatz, starting in LO (true frame).
 // Layer 0 runs as in the CZ form; a layer that starts in HI (odd) turns
 // qubits 5..NQ-1 in the ladder frame, swaps to LO (true frame) and turns
 // qubits 0..4; a later layer that starts in LO turns qubits 0..RB-2 in the
 // ladder frame, qubit RB-1 too when it is 4 (lane swap), swaps to HI and
 // turns the rest.  Ends in the ladder frame, in LO (layers even) or HI.
-template <typename T, int NQ>
-__device__ __forceinline__ void forward_layers_ladder(T* re, T* im, cplx<T>* S, const T* trig, int layers,
-                                                      int lane) {
+template <typename T, int NQ, typename Buf>
+__device__ __forceinline__ void forward_layers_ladder(T* re, T* im, Buf S, const T* trig, int layers, int lane) {
     constexpr int RB = Lay<NQ, false>::RB;
     ry_range<T, NQ, false, 0, 0, NQ>(re, im, lane, trig, 0);
     relayout<T, NQ, false>(re, im, S, lane);
@@ -374,12 +444,24 @@ __device__ __forceinline__ void store_state(const T* re, const T* im, cplx<T>* S
     __syncthreads();
 }
 
+// One component of the registers to a planar image, natural order, S^p applied.
+template <typename T, int NQ, bool HI>
+__device__ __forceinline__ void store_plane(const T* x, T* P, int lane, int p) {
+    constexpr int R = Lay<NQ, HI>::R;
+    const LadderSign<NQ, HI> ls(lane);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const bool flip = p && ls.flip(r);
+        P[pad_slot(Lay<NQ, HI>::g(lane, r))] = flip ? -x[r] : x[r];
+    }
+    __syncthreads();
+}
+
 // Forward pass of the ansatz on the registers (both halves), starting in
 // layout LO with p = 0.  Ends in LO (layers even) or HI (odd) with
 // p = layers mod 2.
-template <typename T, int NQ>
-__device__ __forceinline__ void forward_layers(T* re, T* im, cplx<T>* S, const T* trig, int layers,
-                                               int lane) {
+template <typename T, int NQ, typename Buf>
+__device__ __forceinline__ void forward_layers(T* re, T* im, Buf S, const T* trig, int layers, int lane) {
     int l = 0;
     for (; l + 1 < layers; l += 2) {
         // even layer (p = 0): LO qubits, swap, remaining HI qubits
