@@ -307,14 +307,17 @@ __device__ __forceinline__ void measure_suffix_bvec(cplx<T>* S, dvq_pauli pl, dv
 }
 
 // Literal form: one wavefront simulates one circuit, every gate.
-// (No occupancy bound: at n = 10 in float32 the kernel takes 144 VGPRs,
-// three wavefronts per SIMD; bounding it to 128 for four spills to scratch
-// and measured 4 % slower.)
-// Planar LDS image for float64 states with b = |+>: two wavefronts per
-// SIMD instead of one (the interleaved image would take 33 KB per wave).
+// (No occupancy bound in the launch bounds: bounding the float32 kernel to
+// 128 VGPRs for four wavefronts per SIMD spilled to scratch and measured
+// 4 % slower.)
+// The literal kernel keeps a planar LDS image when b = |+> (the general-b
+// suffix works on the interleaved one): half the LDS per wavefront, so the
+// register count sets the occupancy.  n = 10: float32 three wavefronts per
+// SIMD (CZ, 166 VGPRs; was 2.25 with the 17 KB interleaved image), four
+// with the CNOT ladder; float64 two (was one, 33 KB).
 template <typename T, bool BVEC>
 __host__ __device__ constexpr bool planar_lds() {
-    return sizeof(T) == 8 && !BVEC;
+    return !BVEC;
 }
 
 template <typename T, int NQ, int ENT, bool BVEC>
