@@ -193,47 +193,48 @@ __device__ __forceinline__ void measure_suffix_pair(const cplx<T>* S, SignedPerm
 
 // measure_suffix on a planar image, from the registers prefix_registers
 // left: the final state goes to LDS one component at a time (with the
-// pending ladder sign or frame) and each lane gathers, per component, its
-// ancilla = 0 amplitudes and the permuted ancilla = 1 amplitudes; then the
-// same S^dagger / H / <Z_anc> as measure_suffix.
+// pending ladder sign or frame).  After the real parts each lane keeps its
+// ancilla = 0 amplitudes' real parts and the real parts of the permuted
+// ancilla = 1 amplitudes; with the imaginary parts it completes each pair
+// and applies the same S^dagger / H / <Z_anc> as measure_suffix.
+template <typename T, int NQ, int ENT>
+__device__ __forceinline__ void store_final_plane(const T* x, T* P, int layers, int lane) {
+    if constexpr (ENT == DVQ_ENT_CZ_LADDER) {
+        if (layers & 1)
+            store_plane<T, NQ, true>(x, P, lane, 1);
+        else
+            store_plane<T, NQ, false>(x, P, lane, 0);
+    } else {
+        if (layers & 1)
+            store_plane_ladder_lo<T, NQ, false>(x, P, lane);
+        else
+            store_plane_ladder_lo<T, NQ, true>(x, P, lane);
+    }
+}
+
 template <typename T, int NQ, int ENT>
 __device__ __forceinline__ T measure_planar(T* re, T* im, T* P, SignedPerm sp, int imag, int layers, int lane) {
     constexpr int N = 1 << NQ, KPL = N / 64;
     const T r2 = (T)0.70710678118654752440;
-    const bool odd = layers & 1;
     if constexpr (ENT != DVQ_ENT_CZ_LADDER)
-        if (odd) relayout_ladder<T, NQ, true>(re, im, P, lane);  // HI ladder frame -> LO true frame
+        if (layers & 1) relayout_ladder<T, NQ, true>(re, im, P, lane);  // HI ladder frame -> LO true frame
     const SuffixLane sl = suffix_lane(sp, lane);
-    T a0r[KPL], a0i[KPL], gr[KPL], gi[KPL];
+    T a0r[KPL], gr[KPL];
+    store_final_plane<T, NQ, ENT>(re, P, layers, lane);
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const T* x = c ? im : re;
-        if constexpr (ENT == DVQ_ENT_CZ_LADDER) {
-            if (odd)
-                store_plane<T, NQ, true>(x, P, lane, 1);
-            else
-                store_plane<T, NQ, false>(x, P, lane, 0);
-        } else {
-            if (odd)
-                store_plane_ladder_lo<T, NQ, false>(x, P, lane);
-            else
-                store_plane_ladder_lo<T, NQ, true>(x, P, lane);
-        }
-        T* a0 = c ? a0i : a0r;
-        T* gx = c ? gi : gr;
-#pragma unroll
-        for (int i = 0; i < KPL; ++i) {
-            a0[i] = P[pad_slot(lane + 64 * i)];
-            gx[i] = P[suffix_slot(sl, N, i)];
-        }
-        __syncthreads();  // every lane has read this component
+    for (int i = 0; i < KPL; ++i) {
+        a0r[i] = P[pad_slot(lane + 64 * i)];
+        gr[i] = P[suffix_slot(sl, N, i)];
     }
+    __syncthreads();  // every lane has read the real parts
+    store_final_plane<T, NQ, ENT>(im, P, layers, lane);
     T z = 0;
 #pragma unroll
     for (int i = 0; i < KPL; ++i) {
-        const cplx<T> a1 = mul_ipow(cplx<T>{gr[i], gi[i]}, suffix_pow(sl, i) + (imag ? 3 : 0));
-        const T b0r = (a0r[i] + a1.re) * r2, b0i = (a0i[i] + a1.im) * r2;
-        const T b1r = (a0r[i] - a1.re) * r2, b1i = (a0i[i] - a1.im) * r2;
+        const T a0i = P[pad_slot(lane + 64 * i)];
+        const cplx<T> a1 = mul_ipow(cplx<T>{gr[i], P[suffix_slot(sl, N, i)]}, suffix_pow(sl, i) + (imag ? 3 : 0));
+        const T b0r = (a0r[i] + a1.re) * r2, b0i = (a0i + a1.im) * r2;
+        const T b1r = (a0r[i] - a1.re) * r2, b1i = (a0i - a1.im) * r2;
         z += (b0r * b0r + b0i * b0i) - (b1r * b1r + b1i * b1i);
     }
     return wave_sum(z);
