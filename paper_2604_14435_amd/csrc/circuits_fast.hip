@@ -313,9 +313,9 @@ __device__ __forceinline__ void measure_suffix_bvec(cplx<T>* S, dvq_pauli pl, dv
 // 4 % slower.)
 // The literal kernel keeps a planar LDS image when b = |+> (the general-b
 // suffix works on the interleaved one): half the LDS per wavefront, so the
-// register count sets the occupancy.  n = 10: float32 three wavefronts per
-// SIMD (CZ, 166 VGPRs; was 2.25 with the 17 KB interleaved image), four
-// with the CNOT ladder; float64 two (was one, 33 KB).
+// register count sets the occupancy.  n = 10: float32 four wavefronts per
+// SIMD (127 VGPRs with the CZ ladder, 125 with CNOT; 2.25 with the 17 KB
+// interleaved image); float64 two (one with the 33 KB interleaved image).
 template <typename T, bool BVEC>
 __host__ __device__ constexpr bool planar_lds() {
     return !BVEC;
