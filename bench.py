@@ -12,7 +12,11 @@ One timed step = one VQLS iteration of the fast form:
   gradient (complex64 states, on a second stream beside the circuits: both
   read the angles only) and the gradient-descent update after the gradient;
   the cost of each step is assembled on the second stream while the next
-  step's circuits run (two sets of term buffers).
+  step's circuits run (two sets of term buffers).  The timed steps are
+  replayed from two HIP graphs holding exactly these launches
+  (`paper_2604_14435_amd.graphs`); the same steps launched eagerly, with
+  HIP events around every circuit kernel, give the kernel time of the
+  roofline and the eager step time.
 The plain form (complex128 states, gradient by the parameter-shift rule:
 (2P + 1) x 90,112 circuits per iteration) is timed beside it.
 
@@ -845,6 +849,8 @@ def main() -> int:
                     help="oracle circuit sample on every usable core")
     ap.add_argument("--cpu-full-limit", type=float, default=60.0,
                     help="run the whole oracle cost evaluation on every core if it takes at most this long")
+    ap.add_argument("--ramp-s", type=float, default=0.5,
+                    help="seconds of untimed eager steps before the timed sections (GPU clock ramp)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (calibrates HBM counters)")
@@ -942,18 +948,41 @@ def main() -> int:
         with torch.cuda.stream(side_s):
             api.vqls_cost(coeffs, n, "local", bb, dd, out=(cc, pp))
 
+    # The timed steps replay two HIP graphs holding exactly the launches of
+    # fast_step (the graphs are built first, on their own copy of theta).
+    from paper_2604_14435_amd.graphs import FastGradientDescent
+    theta_g = theta0.clone().view(1, -1)
+    fg = FastGradientDescent(an, coeffs, strings, theta_g, ETA)
+    # The GPU is idle until here and its clock rises over the first few
+    # hundred milliseconds of sustained work: `--ramp-s` seconds of untimed
+    # eager steps come first.
     theta = theta0.clone()
     for _ in range(args.warmup):
         fast_step(theta, False)
     torch.cuda.synchronize()
+    ramp_steps, t_ramp = 0, time.perf_counter()
+    while time.perf_counter() - t_ramp < args.ramp_s:
+        for _ in range(50):
+            fast_step(theta, False)
+        ramp_steps += 50
+        torch.cuda.synchronize()
+    fg.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fg.step(args.steps)
+    torch.cuda.synchronize()
+    fast_s = (time.perf_counter() - t0) / args.steps
+    del fg
+    # the same steps launched eagerly, with HIP events around every circuit
+    # kernel: the roofline's kernel time
     t0 = time.perf_counter()
     for _ in range(args.steps):
         fast_step(theta, True)
     torch.cuda.synchronize()
-    fast_s = (time.perf_counter() - t0) / args.steps
+    eager_s = (time.perf_counter() - t0) / args.steps
     kern_ms = sum(a.elapsed_time(b) for a, b in ev) / len(ev)
 
-    progress(f"fast form: {fast_s * 1e3:.3f} ms per iteration")
+    progress(f"fast form: {fast_s * 1e3:.3f} ms per iteration (graphs), {eager_s * 1e3:.3f} eager")
     # plain form: complex128 circuits + parameter-shift gradient
     ws = api.ShiftWorkspace(an, L, "local", dev)
     Cp = torch.empty(1, dtype=torch.float64, device=dev)
@@ -1055,7 +1084,10 @@ def main() -> int:
         "config": {"workload": "toeplitz_n10_L64", "n": n, "L": int(L), "layers": layers,
                    "entangler": "cz", "cost": "local", "b": "plus", "tau": TAU,
                    "circuits_per_evaluation": int(circuits), "parallelism": "1 GPU"},
-        "s_per_vqls_iter": {"fp32_adjoint": round(fast_s, 6), "plain_fp64_shift": round(plain_s, 6)},
+        "s_per_vqls_iter": {"fp32_adjoint": round(fast_s, 6), "plain_fp64_shift": round(plain_s, 6),
+                            "fp32_adjoint_eager_launches": round(eager_s, 6)},
+        "fast_step": {"launch": "HIP graphs (two, alternating term buffers), replayed",
+                      "eager_ramp": {"seconds": args.ramp_s, "steps": ramp_steps}},
         "circuits_per_s": {"fp32_adjoint": round(circuits / fast_s, 1),
                            "plain_fp64_shift": round(plain_circuits / plain_s, 1)},
         "per_iter_speedup": round(plain_s / fast_s, 2),
