@@ -13,7 +13,8 @@ libdvq.so:
     the adjoint sweep alone, complex128 or complex64 states (complex128: the
     same values as the plain form to rounding, the shift rule being exact
     for RY gates).
-Each evaluation ends with one device-to-host copy of (cost, gradient).
+Each evaluation ends with one device-to-host copy of (cost, gradient); its
+launches are replayed from a HIP graph after the first call.
 """
 from __future__ import annotations
 
@@ -41,10 +42,16 @@ class Trace:
 
 
 class Evaluator:
-    """Cost and gradient of one system at one angle vector, on the GPU."""
+    """Cost and gradient of one system at one angle vector, on the GPU.
+
+    The evaluation writes (cost, gradient) straight into one device buffer,
+    copied to pinned host memory in one transfer.  With `graph` (default)
+    the evaluation's launches are captured once, after a first eager call,
+    and replayed: only the angles' upload, the replay and the result's
+    download remain per call."""
 
     def __init__(self, ansatz: api.AnsatzSpec, coeffs: torch.Tensor, strings: torch.Tensor, form: str,
-                 kind: str = "local", b_kind: str = "plus", b=None):
+                 kind: str = "local", b_kind: str = "plus", b=None, graph: bool = True):
         if form not in ("f32", "f64", "f64-adjoint", "f32-adjoint"):
             raise ValueError(f"unknown form {form!r}")
         self.an, self.coeffs, self.strings, self.form = ansatz, coeffs, strings, form
@@ -54,23 +61,26 @@ class Evaluator:
         L = coeffs.shape[0]
         n, P = ansatz.n, ansatz.P
         self.theta = torch.empty((1, P), dtype=torch.float64, device=dev)
-        self.C = torch.empty(1, dtype=torch.float64, device=dev)
-        self.g = torch.empty((1, P), dtype=torch.float64, device=dev)
-        self.Ca = torch.empty(1, dtype=torch.float64, device=dev)
+        self.theta_host = torch.empty(P, dtype=torch.float64, pin_memory=True)
+        self.packed = torch.empty(P + 1, dtype=torch.float64, device=dev)  # (C, grad)
         self.out_host = torch.empty(P + 1, dtype=torch.float64, pin_memory=True)
-        self.packed = torch.empty(P + 1, dtype=torch.float64, device=dev)
+        self.C = self.packed[0:1]
+        self.g = self.packed[1:].view(1, P)
         if form == "f32":
             other = (1, n, L, L) if kind == "local" else (1, L)
             self.beta = torch.empty((1, L, L), dtype=torch.complex128, device=dev)
             self.other = torch.empty(other, dtype=torch.complex128, device=dev)
             self.parts = torch.empty((1, 2), dtype=torch.complex128, device=dev)
+            self.Ca = torch.empty(1, dtype=torch.float64, device=dev)
             self.side = torch.cuda.Stream(device=dev)  # default priority
         elif form == "f64":
             self.ws = api.ShiftWorkspace(ansatz, L, kind, dev)
+        self.use_graph = graph
+        self.graph = None
 
-    def __call__(self, theta: np.ndarray) -> tuple[float, np.ndarray]:
+    def _launch(self) -> None:
+        """The evaluation at self.theta, on the current stream."""
         main = torch.cuda.current_stream(self.dev)
-        self.theta.copy_(torch.from_numpy(np.asarray(theta, dtype=np.float64)).view(1, -1))
         if self.form == "f32":
             self.side.wait_stream(main)
             with torch.cuda.stream(self.side):
@@ -86,8 +96,20 @@ class Evaluator:
         else:
             api.vqls_grad_adjoint(self.an, self.theta, self.coeffs, self.strings, self.kind, self.form[:3],
                                   b_kind=self.b_kind, b=self.b, out=(self.C, self.g))
-        self.packed[0:1].copy_(self.C)
-        self.packed[1:].copy_(self.g[0])
+
+    def __call__(self, theta: np.ndarray) -> tuple[float, np.ndarray]:
+        self.theta_host.numpy()[:] = np.asarray(theta, dtype=np.float64)
+        self.theta[0].copy_(self.theta_host, non_blocking=True)
+        if self.graph is not None:
+            self.graph.replay()
+        else:
+            self._launch()
+            if self.use_graph:  # capture after the first (eager, validating) call
+                torch.cuda.synchronize(self.dev)
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g, stream=torch.cuda.Stream(device=self.dev)):
+                    self._launch()
+                self.graph = g
         self.out_host.copy_(self.packed)  # synchronous: waits for the evaluation
         v = self.out_host.numpy()
         return float(v[0]), v[1:].copy()

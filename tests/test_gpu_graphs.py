@@ -49,3 +49,24 @@ def test_graph_steps_equal_eager_steps(n, layers, ent, kind, b_kind):
     want = api.vqls_cost(coeffs, n, kind, beta, other)[0].item()
     assert C == want
     assert np.isfinite(C)
+
+
+@pytest.mark.parametrize("n,layers,form", [(10, 4, "f32"), (10, 3, "f32-adjoint"), (4, 2, "f64"), (4, 2, "f64-adjoint")])
+def test_evaluator_graph_replays_equal_eager_calls(n, layers, form):
+    """The L-BFGS evaluator replaying its HIP graph returns what eager
+    launches return, call after call, for changing angles."""
+    from paper_2604_14435_amd.optim import Evaluator
+
+    A = torch.from_numpy(toeplitz(n, 1.0, -0.45)).to(DEV)
+    coeffs, strings, _ = api.pauli_decompose(A, tau=0.01)
+    an = api.AnsatzSpec(n, layers, "cz")
+    eg = Evaluator(an, coeffs, strings, form, graph=True)
+    ee = Evaluator(an, coeffs, strings, form, graph=False)
+    rng = np.random.default_rng(7)
+    th = theta_uniform(an.P, seed=2)
+    for i in range(6):
+        cg, gg = eg(th)
+        ce, ge = ee(th)
+        assert cg == ce and np.array_equal(gg, ge), i
+        th = th - 0.1 * ge + 0.01 * rng.standard_normal(an.P)
+    assert eg.graph is not None and ee.graph is None
