@@ -914,7 +914,7 @@ def main() -> int:
     # two sets of term buffers: the cost of step k reads one while the
     # circuits of step k + 1 write the other
     bufs = [(beta, delta, C, parts),
-            (torch.empty_like(beta), torch.empty_like(delta), torch.empty_like(C), torch.empty_like(parts))]
+            (torch.zeros_like(beta), torch.zeros_like(delta), torch.zeros_like(C), torch.zeros_like(parts))]
     step_no = [0]
 
     def fast_step(theta, record):

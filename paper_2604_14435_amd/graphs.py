@@ -37,11 +37,11 @@ class FastGradientDescent:
         n, L, P = ansatz.n, strings.shape[0], ansatz.P
         other = (1, n, L, L) if kind == "local" else (1, L)
 
-        def term_set():
-            return (torch.empty((1, L, L), dtype=torch.complex128, device=dev),
-                    torch.empty(other, dtype=torch.complex128, device=dev),
-                    torch.empty(1, dtype=torch.float64, device=dev),
-                    torch.empty((1, 2), dtype=torch.complex128, device=dev))
+        def term_set():  # zeroed: the first step assembles a cost from the other set
+            return (torch.zeros((1, L, L), dtype=torch.complex128, device=dev),
+                    torch.zeros(other, dtype=torch.complex128, device=dev),
+                    torch.zeros(1, dtype=torch.float64, device=dev),
+                    torch.zeros((1, 2), dtype=torch.complex128, device=dev))
 
         self.bufs = [term_set(), term_set()]
         self.Ca = torch.empty(1, dtype=torch.float64, device=dev)
