@@ -307,18 +307,114 @@ __device__ __forceinline__ void measure_suffix_bvec(cplx<T>* S, dvq_pauli pl, dv
     measure_suffix_pair<T, NQ>(S, sp, lane, zre, zim, N);
 }
 
+// measure_suffix_bvec on a planar image, from the registers prefix_registers
+// left (literal kernel, one part per circuit).  The final state goes to LDS
+// one component at a time; each lane keeps its ancilla = 0 amplitudes and
+// gathers u = A_m psi_1; the wave sums give H Z_j H u in registers, which
+// goes back through the ancilla = 1 half of the image one component at a
+// time, gathered through A_l and measured as in measure_planar.
+template <typename T, int NQ, int ENT>
+__device__ __forceinline__ T measure_planar_bvec(T* re, T* im, T* P, dvq_pauli pl, dvq_pauli pm, int j,
+                                                 const double* __restrict__ b, int imag, int layers, int lane) {
+    constexpr int N = 1 << NQ, KPL = N / 64;
+    const T r2 = (T)0.70710678118654752440;
+    if constexpr (ENT != DVQ_ENT_CZ_LADDER)
+        if (layers & 1) relayout_ladder<T, NQ, true>(re, im, P, lane);  // HI ladder frame -> LO true frame
+    const double sg = (b[0] > 0.0) ? -1.0 : 1.0;
+    const int pwm = string_pow(pm);
+    T a0r[KPL], a0i[KPL], ur[KPL], ui[KPL];
+    store_final_plane<T, NQ, ENT>(re, P, layers, lane);
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+        const int k = lane + 64 * i;
+        a0r[i] = P[pad_slot(k)];
+        ur[i] = P[pad_slot(N + (k ^ (int)pm.x))];
+    }
+    __syncthreads();  // every lane has read the real parts
+    store_final_plane<T, NQ, ENT>(im, P, layers, lane);
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+        const int k = lane + 64 * i;
+        a0i[i] = P[pad_slot(k)];
+        ui[i] = P[pad_slot(N + (k ^ (int)pm.x))];
+    }
+    __syncthreads();  // every lane has read the imaginary parts
+    T ar = 0, ai = 0, br = 0, bi = 0, ze = 0, om = 0;
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+        const int k = lane + 64 * i;
+        const cplx<T> u = mul_ipow(cplx<T>{ur[i], ui[i]}, pwm + 2 * (int)(__popc((unsigned)k & pm.z) & 1));
+        ur[i] = u.re;
+        ui[i] = u.im;
+        const T w = (T)((k == 0 ? 1.0 : 0.0) - sg * b[k]);
+        const T sw = ((k >> j) & 1) ? -w : w;
+        ar += w * u.re;
+        ai += w * u.im;
+        br += sw * u.re;
+        bi += sw * u.im;
+        ze += sw * w;
+        om += w * w;
+    }
+    ar = wave_sum(ar);
+    ai = wave_sum(ai);
+    br = wave_sum(br);
+    bi = wave_sum(bi);
+    ze = wave_sum(ze);
+    om = wave_sum(om);
+    const T io = (T)1 / om;
+    const T f = (T)4 * ze * io * io;
+    const T c1r = -(T)2 * br * io + f * ar, c1i = -(T)2 * bi * io + f * ai;
+    const T c2r = -(T)2 * ar * io, c2i = -(T)2 * ai * io;
+    // v = H Z_j H u, in place of u
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+        const int k = lane + 64 * i;
+        const T w = (T)((k == 0 ? 1.0 : 0.0) - sg * b[k]);
+        const bool neg = (k >> j) & 1;
+        const T er = neg ? c1r - c2r : c1r + c2r, ei = neg ? c1i - c2i : c1i + c2i;
+        ur[i] = (neg ? -ur[i] : ur[i]) + w * er;
+        ui[i] = (neg ? -ui[i] : ui[i]) + w * ei;
+    }
+    SignedPerm sp;
+    sp.X = pl.x;
+    sp.Z = pl.z;
+    sp.pw = string_pow(pl);
+    const SuffixLane sl = suffix_lane(sp, lane);
+    T gr[KPL];
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) P[pad_slot(N + lane + 64 * i)] = ur[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) gr[i] = P[suffix_slot(sl, N, i)];
+    __syncthreads();  // every lane has read the real parts of A_l v
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) P[pad_slot(N + lane + 64 * i)] = ui[i];
+    __syncthreads();
+    T z = 0;
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+        const cplx<T> a1 = mul_ipow(cplx<T>{gr[i], P[suffix_slot(sl, N, i)]}, suffix_pow(sl, i) + (imag ? 3 : 0));
+        const T b0r = (a0r[i] + a1.re) * r2, b0i = (a0i[i] + a1.im) * r2;
+        const T b1r = (a0r[i] - a1.re) * r2, b1i = (a0i[i] - a1.im) * r2;
+        z += (b0r * b0r + b0i * b0i) - (b1r * b1r + b1i * b1i);
+    }
+    return wave_sum(z);
+}
+
 // Literal form: one wavefront simulates one circuit, every gate.
 // (No occupancy bound in the launch bounds: bounding the float32 kernel to
 // 128 VGPRs for four wavefronts per SIMD spilled to scratch and measured
 // 4 % slower.)
-// The literal kernel keeps a planar LDS image when b = |+> (the general-b
-// suffix works on the interleaved one): half the LDS per wavefront, so the
-// register count sets the occupancy.  n = 10: float32 four wavefronts per
-// SIMD (127 VGPRs with the CZ ladder, 125 with CNOT; 2.25 with the 17 KB
-// interleaved image); float64 two (one with the 33 KB interleaved image).
-template <typename T, bool BVEC>
+// The literal kernel keeps a planar LDS image: half the LDS per wavefront
+// of an interleaved one, so the register count sets the occupancy.  n = 10,
+// b = |+>: float32 four wavefronts per SIMD (127 VGPRs with the CZ ladder,
+// 125 with CNOT; 2.25 with the 17 KB interleaved image); float64 two (one
+// with the 33 KB interleaved image).  General b: three in float32 with the
+// CZ ladder (140 VGPRs); the CNOT ladder's general-b kernel would need 201
+// VGPRs planar and keeps the interleaved image (134 VGPRs, 2.25).
+template <typename T, int ENT, bool BVEC>
 __host__ __device__ constexpr bool planar_lds() {
-    return !BVEC;
+    return !(BVEC && ENT == DVQ_ENT_CNOT_LADDER && sizeof(T) == 4);
 }
 
 template <typename T, int NQ, int ENT, bool BVEC>
@@ -334,14 +430,20 @@ __global__ void __launch_bounds__(64) k_terms_fast(TermsArgs g) {
     const int64_t row = gid / g.per_row;
     const Term t = decode_term(g.c0 + gid - row * g.per_row, g.L, NQ, g.kind);
 
-    if constexpr (planar_lds<T, BVEC>()) {
+    if constexpr (planar_lds<T, ENT, BVEC>()) {
         T* Pl = reinterpret_cast<T*>(smem);
         T* trig = Pl + NSLOT;
         constexpr int R = Lay<NQ, false>::R;
         T re[R], im[R];
         prefix_registers<T, NQ, ENT>(g.theta + row * P, g.layers, Pl, trig, lane, re, im);
-        const SignedPerm sp = suffix_perm(g.strings[t.l], g.strings[t.m], t.type, t.j);
-        const T z = measure_planar<T, NQ, ENT>(re, im, Pl, sp, t.part, g.layers, lane);
+        T z;
+        if (BVEC && t.type == kDelta) {
+            z = measure_planar_bvec<T, NQ, ENT>(re, im, Pl, g.strings[t.l], g.strings[t.m], t.j, g.b, t.part,
+                                                g.layers, lane);
+        } else {
+            const SignedPerm sp = suffix_perm(g.strings[t.l], g.strings[t.m], t.type, t.j);
+            z = measure_planar<T, NQ, ENT>(re, im, Pl, sp, t.part, g.layers, lane);
+        }
         if (lane == 0) store_term(g, row, t, (double)z);
         return;
     }
@@ -409,7 +511,7 @@ static size_t fast_lds_bytes(int layers, bool planar = false) {
 
 template <typename T, int NQ, int ENT, bool BVEC>
 static dvq_status launch_fast_ent(const TermsArgs& g, hipStream_t s) {
-    const size_t lds = fast_lds_bytes<T, NQ>(g.layers, planar_lds<T, BVEC>());
+    const size_t lds = fast_lds_bytes<T, NQ>(g.layers, planar_lds<T, ENT, BVEC>());
     DVQ_TRY_HIP(allow_lds((const void*)k_terms_fast<T, NQ, ENT, BVEC>, lds));
     hipLaunchKernelGGL((k_terms_fast<T, NQ, ENT, BVEC>), grid_for(g.total), dim3(64), lds, s, g);
     DVQ_CHECK_LAUNCH("k_terms_fast");
