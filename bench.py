@@ -13,7 +13,7 @@ One timed step = one VQLS iteration of the fast form:
   read the angles only) and the gradient-descent update after the gradient;
   the cost of each step is assembled on the second stream while the next
   step's circuits run (two sets of term buffers).  The timed steps are
-  replayed from two HIP graphs holding exactly these launches
+  replayed from two HIP graphs holding this work
   (`paper_2604_14435_amd.graphs`); the same steps launched eagerly, with
   HIP events around every circuit kernel, give the kernel time of the
   roofline and the eager step time.
@@ -948,8 +948,10 @@ def main() -> int:
         with torch.cuda.stream(side_s):
             api.vqls_cost(coeffs, n, "local", bb, dd, out=(cc, pp))
 
-    # The timed steps replay two HIP graphs holding exactly the launches of
-    # fast_step (the graphs are built first, on their own copy of theta).
+    # The timed steps replay two HIP graphs holding the same work as
+    # fast_step -- adjoint and the previous step's cost on a second stream,
+    # circuits, update (graphs.FastGradientDescent; built first, on their
+    # own copy of theta).
     from paper_2604_14435_amd.graphs import FastGradientDescent
     theta_g = theta0.clone().view(1, -1)
     fg = FastGradientDescent(an, coeffs, strings, theta_g, ETA)
