@@ -20,14 +20,17 @@
 
 namespace dvq {
 
-constexpr int kAdjThreads = 256;
+// Threads per row: 512 covers the 512 amplitude pairs of an n = 10 gate
+// pass in one step (one row runs at a time in an L-BFGS evaluation, so its
+// latency is the evaluation's; 256 threads took 1.4-1.6x longer).
+constexpr int kAdjThreads = 512;
 
 template <typename T>
 __host__ __device__ constexpr size_t adjoint_lds_bytes(int n, int layers, int L) {
     return 3 * (size_t(1) << n) * sizeof(cplx<T>)            // psi, b1, b2
            + (size_t)L * (sizeof(dvq_pauli) + sizeof(dvq_c128))  // strings, coeffs
            + ((2 * sizeof(T) * n * layers + 15) / 16) * 16         // trig
-           + 8 * sizeof(double);                                  // reduction scratch
+           + (kAdjThreads / 64) * sizeof(double);                 // reduction scratch
 }
 
 // out[k] = sum_l w_l (P_l in)[k] with w_l = c_l or conj(c_l).
