@@ -279,9 +279,11 @@ dvq_status dvq_vqls_grad_shift(const dvq_ansatz* ansatz, const double* theta, in
  *   coeffs [L] and strings [L] shared by all rows (per_row_system = 0), or
  *          [B][L] each (per_row_system = 1: row r uses system r).
  *   C [B], grad [B][P] float64 outputs.
- * One workgroup per row; n <= 12.  Rows of the CZ-ladder ansatz at n = 10,
+ * One workgroup per row; n <= 12 (F32) / 11 (F64): three LDS-resident
+ * vectors of 2^n amplitudes per row must fit the 160 KB of a CU, so F64 at
+ * n = 12 returns DVQ_EUNSUPPORTED.  Rows of the CZ-ladder ansatz at n = 10,
  * 11 (F32) and n = 10 (F64) run as one wavefront each with both vectors in
- * registers; other shapes use three LDS-resident vectors per row.
+ * registers; other shapes use the LDS vectors, 512 threads per row.
  */
 dvq_status dvq_vqls_grad_adjoint(const dvq_ansatz* ansatz, const double* theta, int32_t B,
                                  int32_t precision, const dvq_c128* coeffs,
