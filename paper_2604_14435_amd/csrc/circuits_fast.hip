@@ -191,6 +191,31 @@ __device__ __forceinline__ void measure_suffix_pair(const cplx<T>* S, SignedPerm
     zim = wave_sum(zi);
 }
 
+// The phase i^p of the controlled string at amplitude i of a lane,
+// p = pw(lane) + 2 parity(i & zh) (+ 3 for S^dagger): a per-lane rotation
+// i^q = c + i d, the same for every i, times a sign uniform over the wave.
+template <typename T>
+struct PhaseSplit {
+    T c, d;
+    __device__ __forceinline__ PhaseSplit(const SuffixLane& sl, int imag) {
+        const int q = (sl.pw + (imag ? 3 : 0)) & 3;
+        c = (T)((q == 0) - (q == 2));
+        d = (T)((q == 1) - (q == 3));
+    }
+};
+
+// One amplitude pair's share of <Z_anc> after the controlled string (phase
+// i^q times `sgn`, the permuted amplitude g) and the final H, times 2: the
+// H butterfly a0 +- a1 is applied unnormalised and the 1/2 of its two
+// 1/sqrt(2) factors is applied once to the wave's sum.
+template <typename T>
+__device__ __forceinline__ T z_pair2(T a0r, T a0i, T gr, T gi, const PhaseSplit<T>& ph, T sgn) {
+    const T a1r = sgn * fmat(ph.c, gr, -ph.d * gi), a1i = sgn * fmat(ph.d, gr, ph.c * gi);
+    const T b0r = a0r + a1r, b0i = a0i + a1i;
+    const T b1r = a0r - a1r, b1i = a0i - a1i;
+    return (b0r * b0r + b0i * b0i) - (b1r * b1r + b1i * b1i);
+}
+
 // measure_suffix on a planar image, from the registers prefix_registers
 // left: the final state goes to LDS one component at a time (with the
 // pending ladder sign or frame).  After the real parts each lane keeps its
@@ -215,7 +240,6 @@ __device__ __forceinline__ void store_final_plane(const T* x, T* P, int layers, 
 template <typename T, int NQ, int ENT>
 __device__ __forceinline__ T measure_planar(T* re, T* im, T* P, SignedPerm sp, int imag, int layers, int lane) {
     constexpr int N = 1 << NQ, KPL = N / 64;
-    const T r2 = (T)0.70710678118654752440;
     if constexpr (ENT != DVQ_ENT_CZ_LADDER)
         if (layers & 1) relayout_ladder<T, NQ, true>(re, im, P, lane);  // HI ladder frame -> LO true frame
     const SuffixLane sl = suffix_lane(sp, lane);
@@ -228,16 +252,15 @@ __device__ __forceinline__ T measure_planar(T* re, T* im, T* P, SignedPerm sp, i
     }
     __syncthreads();  // every lane has read the real parts
     store_final_plane<T, NQ, ENT>(im, P, layers, lane);
+    const PhaseSplit<T> ph(sl, imag);
     T z = 0;
 #pragma unroll
     for (int i = 0; i < KPL; ++i) {
         const T a0i = P[pad_slot(lane + 64 * i)];
-        const cplx<T> a1 = mul_ipow(cplx<T>{gr[i], P[suffix_slot(sl, N, i)]}, suffix_pow(sl, i) + (imag ? 3 : 0));
-        const T b0r = (a0r[i] + a1.re) * r2, b0i = (a0i + a1.im) * r2;
-        const T b1r = (a0r[i] - a1.re) * r2, b1i = (a0i - a1.im) * r2;
-        z += (b0r * b0r + b0i * b0i) - (b1r * b1r + b1i * b1i);
+        const T sgn = (__popc((unsigned)(i & sl.zh)) & 1) ? (T)-1 : (T)1;
+        z += z_pair2(a0r[i], a0i, gr[i], P[suffix_slot(sl, N, i)], ph, sgn);
     }
-    return wave_sum(z);
+    return (T)0.5 * wave_sum(z);
 }
 
 // Phase power of one Pauli string: (P v)[k] = i^p (-1)^{z.k} v[k ^ x] with
@@ -317,7 +340,6 @@ template <typename T, int NQ, int ENT>
 __device__ __forceinline__ T measure_planar_bvec(T* re, T* im, T* P, dvq_pauli pl, dvq_pauli pm, int j,
                                                  const double* __restrict__ b, int imag, int layers, int lane) {
     constexpr int N = 1 << NQ, KPL = N / 64;
-    const T r2 = (T)0.70710678118654752440;
     if constexpr (ENT != DVQ_ENT_CZ_LADDER)
         if (layers & 1) relayout_ladder<T, NQ, true>(re, im, P, lane);  // HI ladder frame -> LO true frame
     const double sg = (b[0] > 0.0) ? -1.0 : 1.0;
@@ -390,15 +412,14 @@ __device__ __forceinline__ T measure_planar_bvec(T* re, T* im, T* P, dvq_pauli p
 #pragma unroll
     for (int i = 0; i < KPL; ++i) P[pad_slot(N + lane + 64 * i)] = ui[i];
     __syncthreads();
+    const PhaseSplit<T> ph(sl, imag);
     T z = 0;
 #pragma unroll
     for (int i = 0; i < KPL; ++i) {
-        const cplx<T> a1 = mul_ipow(cplx<T>{gr[i], P[suffix_slot(sl, N, i)]}, suffix_pow(sl, i) + (imag ? 3 : 0));
-        const T b0r = (a0r[i] + a1.re) * r2, b0i = (a0i[i] + a1.im) * r2;
-        const T b1r = (a0r[i] - a1.re) * r2, b1i = (a0i[i] - a1.im) * r2;
-        z += (b0r * b0r + b0i * b0i) - (b1r * b1r + b1i * b1i);
+        const T sgn = (__popc((unsigned)(i & sl.zh)) & 1) ? (T)-1 : (T)1;
+        z += z_pair2(a0r[i], a0i[i], gr[i], P[suffix_slot(sl, N, i)], ph, sgn);
     }
-    return wave_sum(z);
+    return (T)0.5 * wave_sum(z);
 }
 
 // Literal form: one wavefront simulates one circuit, every gate.
