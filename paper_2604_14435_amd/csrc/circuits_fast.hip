@@ -137,60 +137,6 @@ __device__ __forceinline__ int suffix_pow(const SuffixLane& sl, int i) {
     return sl.pw + 2 * (int)(__popc((unsigned)(i & sl.zh)) & 1);
 }
 
-// <Z_anc> after applying U to the ancilla = 1 half, S^dagger (imag) and the
-// final H, summed over the lane's basis states and reduced over the wave.
-template <typename T, int NQ>
-__device__ __forceinline__ T measure_suffix(const cplx<T>* S, SignedPerm sp, int imag, int lane) {
-    constexpr int N = 1 << NQ;
-    const T r2 = (T)0.70710678118654752440;
-    const SuffixLane sl = suffix_lane(sp, lane);
-    T z = 0;
-#pragma unroll 4
-    for (int i = 0; i < N / 64; ++i) {
-        const int k = lane + 64 * i;
-        const cplx<T> a0 = S[pad_slot(k)];
-        const cplx<T> a1 = mul_ipow(S[suffix_slot(sl, N, i)], suffix_pow(sl, i) + (imag ? 3 : 0));
-        const T b0r = (a0.re + a1.re) * r2, b0i = (a0.im + a1.im) * r2;
-        const T b1r = (a0.re - a1.re) * r2, b1i = (a0.im - a1.im) * r2;
-        z += (b0r * b0r + b0i * b0i) - (b1r * b1r + b1i * b1i);
-    }
-    return wave_sum(z);
-}
-
-// Both circuits (real, imaginary) of one term from one pass over the state:
-// the gathers and phases are shared, each circuit gets its own S^dagger,
-// H and <Z_anc>.
-// `src` is the offset of the half the controlled gates read (N: the
-// ancilla = 1 half; 0: the other half, which holds the same amplitudes,
-// when half 1 serves as scratch).
-template <typename T, int NQ>
-__device__ __forceinline__ void measure_suffix_pair(const cplx<T>* S, SignedPerm sp, int lane, T& zre,
-                                                    T& zim, int src = 1 << NQ) {
-    constexpr int N = 1 << NQ;
-    const T r2 = (T)0.70710678118654752440;
-    const SuffixLane sl = suffix_lane(sp, lane);
-    T zr = 0, zi = 0;
-#pragma unroll 4
-    for (int i = 0; i < N / 64; ++i) {
-        const int k = lane + 64 * i;
-        const cplx<T> a0 = S[pad_slot(k)];
-        const cplx<T> a1 = mul_ipow(S[suffix_slot(sl, src, i)], suffix_pow(sl, i));
-        // real-part circuit: H then <Z>
-        T b0r = (a0.re + a1.re) * r2, b0i = (a0.im + a1.im) * r2;
-        T b1r = (a0.re - a1.re) * r2, b1i = (a0.im - a1.im) * r2;
-        zr += (b0r * b0r + b0i * b0i) - (b1r * b1r + b1i * b1i);
-        // imaginary-part circuit: S^dagger (a1 -> -i a1), H, <Z>
-        const T c1r = a1.im, c1i = -a1.re;
-        b0r = (a0.re + c1r) * r2;
-        b0i = (a0.im + c1i) * r2;
-        b1r = (a0.re - c1r) * r2;
-        b1i = (a0.im - c1i) * r2;
-        zi += (b0r * b0r + b0i * b0i) - (b1r * b1r + b1i * b1i);
-    }
-    zre = wave_sum(zr);
-    zim = wave_sum(zi);
-}
-
 // The phase i^p of the controlled string at amplitude i of a lane,
 // p = pw(lane) + 2 parity(i & zh) (+ 3 for S^dagger): a per-lane rotation
 // i^q = c + i d, the same for every i, times a sign uniform over the wave.
@@ -214,6 +160,49 @@ __device__ __forceinline__ T z_pair2(T a0r, T a0i, T gr, T gi, const PhaseSplit<
     const T b0r = a0r + a1r, b0i = a0i + a1i;
     const T b1r = a0r - a1r, b1i = a0i - a1i;
     return (b0r * b0r + b0i * b0i) - (b1r * b1r + b1i * b1i);
+}
+
+// <Z_anc> after applying U to the ancilla = 1 half, S^dagger (imag) and the
+// final H, summed over the lane's basis states and reduced over the wave.
+template <typename T, int NQ>
+__device__ __forceinline__ T measure_suffix(const cplx<T>* S, SignedPerm sp, int imag, int lane) {
+    constexpr int N = 1 << NQ;
+    const SuffixLane sl = suffix_lane(sp, lane);
+    const PhaseSplit<T> ph(sl, imag);
+    T z = 0;
+#pragma unroll 4
+    for (int i = 0; i < N / 64; ++i) {
+        const cplx<T> a0 = S[pad_slot(lane + 64 * i)];
+        const cplx<T> g = S[suffix_slot(sl, N, i)];
+        const T sgn = (__popc((unsigned)(i & sl.zh)) & 1) ? (T)-1 : (T)1;
+        z += z_pair2(a0.re, a0.im, g.re, g.im, ph, sgn);
+    }
+    return (T)0.5 * wave_sum(z);
+}
+
+// Both circuits (real, imaginary) of one term from one pass over the state:
+// the gathers and phases are shared, each circuit gets its own S^dagger,
+// H and <Z_anc>.
+// `src` is the offset of the half the controlled gates read (N: the
+// ancilla = 1 half; 0: the other half, which holds the same amplitudes,
+// when half 1 serves as scratch).
+template <typename T, int NQ>
+__device__ __forceinline__ void measure_suffix_pair(const cplx<T>* S, SignedPerm sp, int lane, T& zre,
+                                                    T& zim, int src = 1 << NQ) {
+    constexpr int N = 1 << NQ;
+    const SuffixLane sl = suffix_lane(sp, lane);
+    const PhaseSplit<T> pre(sl, 0), pim(sl, 1);
+    T zr = 0, zi = 0;
+#pragma unroll 4
+    for (int i = 0; i < N / 64; ++i) {
+        const cplx<T> a0 = S[pad_slot(lane + 64 * i)];
+        const cplx<T> g = S[suffix_slot(sl, src, i)];
+        const T sgn = (__popc((unsigned)(i & sl.zh)) & 1) ? (T)-1 : (T)1;
+        zr += z_pair2(a0.re, a0.im, g.re, g.im, pre, sgn);  // real-part circuit: H, <Z>
+        zi += z_pair2(a0.re, a0.im, g.re, g.im, pim, sgn);  // imaginary part: S^dagger, H, <Z>
+    }
+    zre = (T)0.5 * wave_sum(zr);
+    zim = (T)0.5 * wave_sum(zi);
 }
 
 // measure_suffix on a planar image, from the registers prefix_registers
