@@ -1015,6 +1015,18 @@ def main() -> int:
     e1.record()
     torch.cuda.synchronize()
     shared_ms = e0.elapsed_time(e1) / args.steps
+    # the complex64 adjoint alone (one wavefront; it runs beside the circuits
+    # on the second stream of every step)
+    Cadj = torch.empty(1, dtype=torch.float64, device=dev)
+    gadj = torch.empty((1, P), dtype=torch.float64, device=dev)
+    th1 = theta0.view(1, -1)
+    api.vqls_grad_adjoint(an, th1, coeffs, strings, "local", "f32", out=(Cadj, gadj))
+    e0.record()
+    for _ in range(args.steps):
+        api.vqls_grad_adjoint(an, th1, coeffs, strings, "local", "f32", out=(Cadj, gadj))
+    e1.record()
+    torch.cuda.synchronize()
+    adjoint_ms = e0.elapsed_time(e1) / args.steps
 
     # FWHT decomposition of the dense random symmetric 4096 x 4096 matrix
     fwht = None
@@ -1032,12 +1044,26 @@ def main() -> int:
         e1.record()
         torch.cuda.synchronize()
         fwht_ms = e0.elapsed_time(e1) / reps
+        # a streaming kernel with the same bytes: torch's float64 -> complex128
+        # copy of the same matrix (reads 8 B, writes 16 B per entry); one
+        # untimed call first loads its kernel
+        c12.copy_(A12)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            c12.copy_(A12)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_ms = e0.elapsed_time(e1) / reps
         alg_bytes = (8 + 16) * 4 ** 12
         fk = "k_fwht_fused<6,2> (n=12 dense)"
         fwht = {"bound": "hbm", "achieved": round(alg_bytes / (fwht_ms * 1e-3) / 1e9, 1), "peak": 8000.0,
                 "unit": "GB/s", "frac": round(alg_bytes / (fwht_ms * 1e-3) / 8e12, 4),
                 "traffic": measured_traffic(fk), "kernel": fk, "avg_ms": round(fwht_ms, 4),
-                "algorithmic_bytes": alg_bytes}
+                "algorithmic_bytes": alg_bytes,
+                "same_bytes_copy": {"what": "torch float64 -> complex128 copy of the same matrix",
+                                    "ms": round(copy_ms, 4),
+                                    "GB/s": round(alg_bytes / (copy_ms * 1e-3) / 1e9, 1)}}
         del A12, c12, ws12
 
     progress("shared mode and FWHT timed")
@@ -1089,7 +1115,8 @@ def main() -> int:
         "s_per_vqls_iter": {"fp32_adjoint": round(fast_s, 6), "plain_fp64_shift": round(plain_s, 6),
                             "fp32_adjoint_eager_launches": round(eager_s, 6)},
         "fast_step": {"launch": "HIP graphs (two, alternating term buffers), replayed",
-                      "eager_ramp": {"seconds": args.ramp_s, "steps": ramp_steps}},
+                      "eager_ramp": {"seconds": args.ramp_s, "steps": ramp_steps},
+                      "adjoint_alone_ms": round(adjoint_ms, 4)},
         "circuits_per_s": {"fp32_adjoint": round(circuits / fast_s, 1),
                            "plain_fp64_shift": round(plain_circuits / plain_s, 1)},
         "per_iter_speedup": round(plain_s / fast_s, 2),
