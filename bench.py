@@ -43,6 +43,7 @@ METRIC = "circuits/s + s/VQLS-iter @ n=10 L=64: FP32+adjoint+warm-start vs plain
 # hardware-counted float32 flops exceed the 128 flop/clk/CU (78.6 TFLOP/s)
 # of one non-packed FMA per lane per clock, so only the published figure is
 # a ceiling for it.
+GRAPH_UNROLL = 10  # iterations per replayed graph in the timed steps
 FP32_ALU_PEAK = 157.3
 FP64_ALU_PEAK = 78.6
 N_QUBITS, LAYERS, TAU, DIAG, OFFDIAG, ETA = 10, 4, 0.01, 1.0, -0.45, 2.0
@@ -948,13 +949,13 @@ def main() -> int:
         with torch.cuda.stream(side_s):
             api.vqls_cost(coeffs, n, "local", bb, dd, out=(cc, pp))
 
-    # The timed steps replay two HIP graphs holding the same work as
-    # fast_step -- adjoint and the previous step's cost on a second stream,
-    # circuits, update (graphs.FastGradientDescent; built first, on their
-    # own copy of theta).
+    # The timed steps replay HIP graphs holding the same work as fast_step
+    # -- adjoint and the previous step's cost on a second stream, circuits,
+    # update -- GRAPH_UNROLL iterations per graph (graphs.FastGradientDescent;
+    # built first, on their own copy of theta).
     from paper_2604_14435_amd.graphs import FastGradientDescent
     theta_g = theta0.clone().view(1, -1)
-    fg = FastGradientDescent(an, coeffs, strings, theta_g, ETA)
+    fg = FastGradientDescent(an, coeffs, strings, theta_g, ETA, unroll=GRAPH_UNROLL)
     # The GPU is idle until here and its clock rises over the first few
     # hundred milliseconds of sustained work: `--ramp-s` seconds of untimed
     # eager steps come first.
@@ -1114,7 +1115,7 @@ def main() -> int:
                    "circuits_per_evaluation": int(circuits), "parallelism": "1 GPU"},
         "s_per_vqls_iter": {"fp32_adjoint": round(fast_s, 6), "plain_fp64_shift": round(plain_s, 6),
                             "fp32_adjoint_eager_launches": round(eager_s, 6)},
-        "fast_step": {"launch": "HIP graphs (two, alternating term buffers), replayed",
+        "fast_step": {"launch": f"HIP graphs of {GRAPH_UNROLL} iterations (alternating term buffers), replayed",
                       "eager_ramp": {"seconds": args.ramp_s, "steps": ramp_steps},
                       "adjoint_alone_ms": round(adjoint_ms, 4)},
         "circuits_per_s": {"fp32_adjoint": round(circuits / fast_s, 1),

@@ -12,7 +12,10 @@ captured once and replayed: the per-launch host work disappears and the
 cross-stream waits become graph edges.  The term buffers alternate between
 consecutive iterations (the cost of one iteration reads them while the next
 iteration's circuits write the other set), hence two graphs, replayed in
-turn.  The graphs hold no memory set or copy nodes, only library kernels.
+turn.  With `unroll` > 1, runs of that many consecutive iterations are also
+captured as one graph each, so the iterations inside a run follow each
+other without the gap between two graph launches.  The graphs hold no
+memory set or copy nodes, only library kernels.
 """
 from __future__ import annotations
 
@@ -26,7 +29,10 @@ class FastGradientDescent:
     in place by every step."""
 
     def __init__(self, ansatz: api.AnsatzSpec, coeffs: torch.Tensor, strings: torch.Tensor, theta: torch.Tensor,
-                 eta: float, kind: str = "local", b_kind: str = "plus", b: torch.Tensor | None = None):
+                 eta: float, kind: str = "local", b_kind: str = "plus", b: torch.Tensor | None = None,
+                 unroll: int = 1):
+        if unroll < 1:
+            raise ValueError(f"unroll must be >= 1, got {unroll}")
         if theta.dim() != 2 or theta.shape[0] != 1 or theta.shape[1] != ansatz.P:
             raise ValueError(f"theta must be [1, {ansatz.P}], got {tuple(theta.shape)}")
         if theta.dtype != torch.float64 or not theta.is_cuda or not theta.is_contiguous():
@@ -54,13 +60,29 @@ class FastGradientDescent:
         for k in range(2):
             self._step(k, scratch)
         torch.cuda.synchronize(dev)
-        self.graphs = []
-        for k in range(2):
-            g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g, stream=torch.cuda.Stream(device=dev)):
-                self._step(k, self.theta)
-            self.graphs.append(g)
+        self.graphs = [self._capture(k, 1) for k in range(2)]
+        # `unroll` consecutive iterations per graph (one per starting parity):
+        # the iterations inside a graph follow each other without the gap
+        # between two graph launches
+        self.unroll = unroll
+        self.blocks = [self._capture(k, unroll) for k in range(2)] if unroll > 1 else []
+        # one replay of every graph (a graph's first launch carries one-off
+        # costs), then the angles and the term buffers are put back
+        saved = theta.detach().clone()
+        for g in self.graphs + self.blocks:
+            g.replay()
+        self.theta.copy_(saved)
+        for buf in self.bufs:
+            for t in buf:
+                t.zero_()
         torch.cuda.synchronize(dev)
+
+    def _capture(self, k0: int, count: int) -> torch.cuda.CUDAGraph:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=torch.cuda.Stream(device=self.theta.device)):
+            for k in range(k0, k0 + count):
+                self._step(k, self.theta)
+        return g
 
     def _step(self, k: int, theta: torch.Tensor) -> None:
         main = torch.cuda.current_stream(theta.device)
@@ -79,6 +101,10 @@ class FastGradientDescent:
 
     def step(self, count: int = 1) -> None:
         """`count` iterations, launched on the current stream."""
+        while self.blocks and count >= self.unroll:
+            self.blocks[self.k & 1].replay()
+            self.k += self.unroll
+            count -= self.unroll
         for _ in range(count):
             self.graphs[self.k & 1].replay()
             self.k += 1

@@ -51,6 +51,29 @@ def test_graph_steps_equal_eager_steps(n, layers, ent, kind, b_kind):
     assert np.isfinite(C)
 
 
+@pytest.mark.parametrize("unroll", [2, 5])
+def test_unrolled_graphs_equal_single_step_graphs(unroll):
+    """Runs of `unroll` iterations captured as one graph give the angles and
+    the cost of the single-iteration graphs, bit for bit, for step counts
+    that start runs at both parities and leave remainders."""
+    n = 10
+    A = torch.from_numpy(toeplitz(n, 1.0, -0.45)).to(DEV)
+    coeffs, strings, _ = api.pauli_decompose(A, tau=0.01)
+    an = api.AnsatzSpec(n, 4, "cz")
+    th0 = torch.from_numpy(theta_uniform(an.P, seed=3)).to(DEV).view(1, -1)
+    one = FastGradientDescent(an, coeffs, strings, th0.clone(), 0.5)
+    many = FastGradientDescent(an, coeffs, strings, th0.clone(), 0.5, unroll=unroll)
+    for count in (1, unroll, unroll + 1, 2 * unroll + 3):
+        one.step(count)
+        many.step(count)
+        torch.cuda.synchronize()
+        assert one.k == many.k
+        assert torch.equal(one.theta, many.theta), count
+        assert one.last_cost().item() == many.last_cost().item()
+    with pytest.raises(ValueError):
+        FastGradientDescent(an, coeffs, strings, th0.clone(), 0.5, unroll=0)
+
+
 @pytest.mark.parametrize("n,layers,form", [(10, 4, "f32"), (10, 3, "f32-adjoint"), (4, 2, "f64"), (4, 2, "f64-adjoint")])
 def test_evaluator_graph_replays_equal_eager_calls(n, layers, form):
     """The L-BFGS evaluator replaying its HIP graph returns what eager
