@@ -59,6 +59,33 @@ struct Lay {
 // LDS slot of basis index g: one pad amplitude every 32.
 __device__ __forceinline__ int pad_slot(int g) { return g + (g >> 5); }
 
+// pad_slot(Lay<NQ, HI>::g(lane, r)).  With SPLIT, as a per-lane base plus a
+// per-register offset: the lane and register parts of g occupy disjoint
+// bits, and so do their parts above bit 5, so g + (g >> 5) is the sum of the
+// same expression over each part; with r known at compile time the offset
+// becomes the LDS instruction's immediate and the address costs no
+// instruction per register.  The float32 kernels take the split (fewer
+// instructions and registers, one more wavefront per SIMD); the float64
+// kernels measured faster with the combined index and keep it.
+template <int NQ, bool HI, bool SPLIT>
+struct SlotMap {
+    int lg, base;
+    __device__ __forceinline__ explicit SlotMap(int lane)
+        : lg(Lay<NQ, HI>::glane(lane)), base(pad_slot(Lay<NQ, HI>::glane(lane))) {}
+    __host__ __device__ static constexpr int roff(int r) {
+        return Lay<NQ, HI>::greg(r) + (Lay<NQ, HI>::greg(r) >> 5);
+    }
+    __device__ __forceinline__ int operator()(int r) const {
+        if constexpr (SPLIT)
+            return base + roff(r);
+        else
+            return pad_slot(lg | Lay<NQ, HI>::greg(r));
+    }
+};
+
+template <typename T>
+constexpr bool kSplitSlots = sizeof(T) == 4;
+
 // Sign of the pair (r0, r0 | bit of Q) under the lazy ladder frame: the lane
 // part is returned by lane_rho, the register part by reg_rho.
 template <int NQ, bool HI, int Q>
@@ -130,12 +157,14 @@ __device__ __forceinline__ void ry_range(T* re, T* im, int lane, const T* trig, 
 template <typename T, int NQ, bool FROM_HI>
 __device__ __forceinline__ void relayout(T* re, T* im, cplx<T>* S, int lane) {
     constexpr int R = Lay<NQ, FROM_HI>::R;
+    const SlotMap<NQ, FROM_HI, kSplitSlots<T>> from(lane);
 #pragma unroll
-    for (int r = 0; r < R; ++r) S[pad_slot(Lay<NQ, FROM_HI>::g(lane, r))] = {re[r], im[r]};
+    for (int r = 0; r < R; ++r) S[from(r)] = {re[r], im[r]};
     __syncthreads();
+    const SlotMap<NQ, !FROM_HI, kSplitSlots<T>> to(lane);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const cplx<T> v = S[pad_slot(Lay<NQ, !FROM_HI>::g(lane, r))];
+        const cplx<T> v = S[to(r)];
         re[r] = v.re;
         im[r] = v.im;
     }
@@ -149,11 +178,13 @@ __device__ __forceinline__ void relayout(T* re, T* im, cplx<T>* S, int lane) {
 template <typename T, int NQ, bool FROM_HI>
 __device__ __forceinline__ void relayout_plane(T* x, T* P, int lane) {
     constexpr int R = Lay<NQ, FROM_HI>::R;
+    const SlotMap<NQ, FROM_HI, kSplitSlots<T>> from(lane);
 #pragma unroll
-    for (int r = 0; r < R; ++r) P[pad_slot(Lay<NQ, FROM_HI>::g(lane, r))] = x[r];
+    for (int r = 0; r < R; ++r) P[from(r)] = x[r];
     __syncthreads();
+    const SlotMap<NQ, !FROM_HI, kSplitSlots<T>> to(lane);
 #pragma unroll
-    for (int r = 0; r < R; ++r) x[r] = P[pad_slot(Lay<NQ, !FROM_HI>::g(lane, r))];
+    for (int r = 0; r < R; ++r) x[r] = P[to(r)];
     __syncthreads();
 }
 
@@ -283,8 +314,9 @@ __device__ __forceinline__ void relayout_ladder(T* re, T* im, cplx<T>* S, int la
     using To = Lay<NQ, !FROM_HI>;
     constexpr int R = From::R;
     constexpr int SPLIT = FROM_HI ? To::RB : 5;
+    const SlotMap<NQ, FROM_HI, kSplitSlots<T>> from(lane);
 #pragma unroll
-    for (int r = 0; r < R; ++r) S[pad_slot(From::g(lane, r))] = {re[r], im[r]};
+    for (int r = 0; r < R; ++r) S[from(r)] = {re[r], im[r]};
     __syncthreads();
     const int ub = ladder_unperm<NQ>(To::glane(lane));
     const int base0 = pad_slot(ub), base1 = pad_slot(ub ^ (1 << SPLIT));
@@ -306,8 +338,9 @@ __device__ __forceinline__ void relayout_ladder_plane(T* x, T* P, int lane) {
     using To = Lay<NQ, !FROM_HI>;
     constexpr int R = From::R;
     constexpr int SPLIT = FROM_HI ? To::RB : 5;
+    const SlotMap<NQ, FROM_HI, kSplitSlots<T>> from(lane);
 #pragma unroll
-    for (int r = 0; r < R; ++r) P[pad_slot(From::g(lane, r))] = x[r];
+    for (int r = 0; r < R; ++r) P[from(r)] = x[r];
     __syncthreads();
     const int ub = ladder_unperm<NQ>(To::glane(lane));
     const int base0 = pad_slot(ub), base1 = pad_slot(ub ^ (1 << SPLIT));
@@ -337,8 +370,9 @@ __device__ __forceinline__ void store_state_ladder(T* re, T* im, cplx<T>* S, int
     constexpr int HM = ((1 << NQ) - 1) & ~((1 << RB) - 1);
     if constexpr (HI) relayout_ladder<T, NQ, true>(re, im, S, lane);
     if constexpr (HI) {
+        const SlotMap<NQ, false, kSplitSlots<T>> lo(lane);
 #pragma unroll
-        for (int r = 0; r < R; ++r) S[pad_slot(Lo::g(lane, r))] = {re[r], im[r]};
+        for (int r = 0; r < R; ++r) S[lo(r)] = {re[r], im[r]};
     } else {
         const int pl = ladder_perm<NQ>(Lo::glane(lane));
         const int base0 = pad_slot(pl), base1 = pad_slot(pl ^ HM);
@@ -360,8 +394,9 @@ __device__ __forceinline__ void store_plane_ladder_lo(const T* x, T* P, int lane
     constexpr int R = Lo::R, RB = Lo::RB;
     constexpr int HM = ((1 << NQ) - 1) & ~((1 << RB) - 1);
     if constexpr (!FRAME) {
+        const SlotMap<NQ, false, kSplitSlots<T>> lo(lane);
 #pragma unroll
-        for (int r = 0; r < R; ++r) P[pad_slot(Lo::g(lane, r))] = x[r];
+        for (int r = 0; r < R; ++r) P[lo(r)] = x[r];
     } else {
         const int pl = ladder_perm<NQ>(Lo::glane(lane));
         const int base0 = pad_slot(pl), base1 = pad_slot(pl ^ HM);
@@ -435,11 +470,11 @@ template <typename T, int NQ, bool HI>
 __device__ __forceinline__ void store_state(const T* re, const T* im, cplx<T>* S, int lane, int p) {
     constexpr int R = Lay<NQ, HI>::R;
     const LadderSign<NQ, HI> ls(lane);
+    const SlotMap<NQ, HI, kSplitSlots<T>> sm(lane);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int g = Lay<NQ, HI>::g(lane, r);
         const bool flip = p && ls.flip(r);
-        S[pad_slot(g)] = flip ? cplx<T>{-re[r], -im[r]} : cplx<T>{re[r], im[r]};
+        S[sm(r)] = flip ? cplx<T>{-re[r], -im[r]} : cplx<T>{re[r], im[r]};
     }
     __syncthreads();
 }
@@ -449,10 +484,11 @@ template <typename T, int NQ, bool HI>
 __device__ __forceinline__ void store_plane(const T* x, T* P, int lane, int p) {
     constexpr int R = Lay<NQ, HI>::R;
     const LadderSign<NQ, HI> ls(lane);
+    const SlotMap<NQ, HI, kSplitSlots<T>> sm(lane);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const bool flip = p && ls.flip(r);
-        P[pad_slot(Lay<NQ, HI>::g(lane, r))] = flip ? -x[r] : x[r];
+        P[sm(r)] = flip ? -x[r] : x[r];
     }
     __syncthreads();
 }
