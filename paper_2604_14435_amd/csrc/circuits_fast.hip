@@ -429,15 +429,19 @@ __host__ __device__ constexpr bool planar_lds() {
 
 // Minimum wavefronts per SIMD the compiler is asked to fit: five for the
 // float32 b = |+> kernels at NQ <= 10 (96 VGPRs with a 28-40 byte spill;
-// the LDS image then allows 18 wavefronts per CU instead of 16); no bound
-// elsewhere (the general-b and larger states would spill heavily).
-template <typename T, int NQ, bool BVEC>
+// the LDS image then allows 18 wavefronts per CU instead of 16), four for
+// the float32 general-b kernel on the planar image (128 VGPRs, 36-byte
+// spill); no bound elsewhere (the interleaved image caps occupancy through
+// LDS, and larger states would spill heavily).
+template <typename T, int NQ, int ENT, bool BVEC>
 constexpr int fast_waves() {
-    return (sizeof(T) == 4 && !BVEC && NQ <= 10) ? 5 : 1;
+    if (sizeof(T) != 4 || NQ > 10) return 1;
+    if (!BVEC) return 5;
+    return planar_lds<T, ENT, BVEC>() ? 4 : 1;
 }
 
 template <typename T, int NQ, int ENT, bool BVEC>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(fast_waves<T, NQ, BVEC>()))) k_terms_fast(TermsArgs g) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(fast_waves<T, NQ, ENT, BVEC>()))) k_terms_fast(TermsArgs g) {
     constexpr int N = 1 << NQ;
     constexpr int NSLOT = 2 * N + (2 * N) / 32;
     extern __shared__ __align__(16) unsigned char smem[];
