@@ -241,15 +241,32 @@ __device__ __forceinline__ T measure_planar(T* re, T* im, T* P, SignedPerm sp, i
     }
     __syncthreads();  // every lane has read the real parts
     store_final_plane<T, NQ, ENT>(im, P, layers, lane);
+    // |a0 + a1|^2 - |a0 - a1|^2 = 4 Re(conj(a0) a1), a1 = sgn (c + i d) g:
+    // 4 sgn (c (a0r gr + a0i gi) + d (a0i gr - a0r gi)).  One of c, d is zero,
+    // the same one in every lane (the lane part of the phase only flips its
+    // sign), so each amplitude pair needs one product pair, and the lane's
+    // c or d multiplies its sum once.
     const PhaseSplit<T> ph(sl, imag);
+    const bool odd = (sp.pw + (imag ? 3 : 0)) & 1;  // wave-uniform: d != 0
     T z = 0;
+    if (!odd) {
 #pragma unroll
-    for (int i = 0; i < KPL; ++i) {
-        const T a0i = P[pad_slot(lane + 64 * i)];
-        const T sgn = (__popc((unsigned)(i & sl.zh)) & 1) ? (T)-1 : (T)1;
-        z += z_pair2(a0r[i], a0i, gr[i], P[suffix_slot(sl, N, i)], ph, sgn);
+        for (int i = 0; i < KPL; ++i) {
+            const T a0i = P[pad_slot(lane + 64 * i)], gi = P[suffix_slot(sl, N, i)];
+            const T sgn = (__popc((unsigned)(i & sl.zh)) & 1) ? (T)-1 : (T)1;
+            z = fmat(sgn, fmat(a0r[i], gr[i], a0i * gi), z);
+        }
+        z *= ph.c;
+    } else {
+#pragma unroll
+        for (int i = 0; i < KPL; ++i) {
+            const T a0i = P[pad_slot(lane + 64 * i)], gi = P[suffix_slot(sl, N, i)];
+            const T sgn = (__popc((unsigned)(i & sl.zh)) & 1) ? (T)-1 : (T)1;
+            z = fmat(sgn, fmat(a0i, gr[i], -(a0r[i] * gi)), z);
+        }
+        z *= ph.d;
     }
-    return (T)0.5 * wave_sum(z);
+    return (T)2 * wave_sum(z);
 }
 
 // Phase power of one Pauli string: (P v)[k] = i^p (-1)^{z.k} v[k ^ x] with
