@@ -154,6 +154,15 @@ struct PhaseSplit {
 // i^q times `sgn`, the permuted amplitude g) and the final H, times 2: the
 // H butterfly a0 +- a1 is applied unnormalised and the 1/2 of its two
 // 1/sqrt(2) factors is applied once to the wave's sum.
+// Two sums give the readout of both circuits of a term without the
+// butterfly: sum over pairs of z_pair2 = 4 (c S1 + d S2) with
+// S1 = sum sgn (a0r gr + a0i gi), S2 = sum sgn (a0i gr - a0r gi).
+template <typename T>
+__device__ __forceinline__ void z_sums(T a0r, T a0i, T gr, T gi, T sgn, T& s1, T& s2) {
+    s1 = fmat(sgn, fmat(a0r, gr, a0i * gi), s1);
+    s2 = fmat(sgn, fmat(a0i, gr, -(a0r * gi)), s2);
+}
+
 template <typename T>
 __device__ __forceinline__ T z_pair2(T a0r, T a0i, T gr, T gi, const PhaseSplit<T>& ph, T sgn) {
     const T a1r = sgn * fmat(ph.c, gr, -ph.d * gi), a1i = sgn * fmat(ph.d, gr, ph.c * gi);
@@ -169,15 +178,15 @@ __device__ __forceinline__ T measure_suffix(const cplx<T>* S, SignedPerm sp, int
     constexpr int N = 1 << NQ;
     const SuffixLane sl = suffix_lane(sp, lane);
     const PhaseSplit<T> ph(sl, imag);
-    T z = 0;
+    T s1 = 0, s2 = 0;
 #pragma unroll 4
     for (int i = 0; i < N / 64; ++i) {
         const cplx<T> a0 = S[pad_slot(lane + 64 * i)];
         const cplx<T> g = S[suffix_slot(sl, N, i)];
         const T sgn = (__popc((unsigned)(i & sl.zh)) & 1) ? (T)-1 : (T)1;
-        z += z_pair2(a0.re, a0.im, g.re, g.im, ph, sgn);
+        z_sums(a0.re, a0.im, g.re, g.im, sgn, s1, s2);
     }
-    return (T)0.5 * wave_sum(z);
+    return (T)2 * wave_sum(fmat(ph.c, s1, ph.d * s2));
 }
 
 // Both circuits (real, imaginary) of one term from one pass over the state:
@@ -191,18 +200,17 @@ __device__ __forceinline__ void measure_suffix_pair(const cplx<T>* S, SignedPerm
                                                     T& zim, int src = 1 << NQ) {
     constexpr int N = 1 << NQ;
     const SuffixLane sl = suffix_lane(sp, lane);
-    const PhaseSplit<T> pre(sl, 0), pim(sl, 1);
-    T zr = 0, zi = 0;
+    const PhaseSplit<T> pre(sl, 0), pim(sl, 1);  // real-part circuit; imaginary part (S^dagger)
+    T s1 = 0, s2 = 0;
 #pragma unroll 4
     for (int i = 0; i < N / 64; ++i) {
         const cplx<T> a0 = S[pad_slot(lane + 64 * i)];
         const cplx<T> g = S[suffix_slot(sl, src, i)];
         const T sgn = (__popc((unsigned)(i & sl.zh)) & 1) ? (T)-1 : (T)1;
-        zr += z_pair2(a0.re, a0.im, g.re, g.im, pre, sgn);  // real-part circuit: H, <Z>
-        zi += z_pair2(a0.re, a0.im, g.re, g.im, pim, sgn);  // imaginary part: S^dagger, H, <Z>
+        z_sums(a0.re, a0.im, g.re, g.im, sgn, s1, s2);
     }
-    zre = (T)0.5 * wave_sum(zr);
-    zim = (T)0.5 * wave_sum(zi);
+    zre = (T)2 * wave_sum(fmat(pre.c, s1, pre.d * s2));
+    zim = (T)2 * wave_sum(fmat(pim.c, s1, pim.d * s2));
 }
 
 // measure_suffix on a planar image, from the registers prefix_registers
