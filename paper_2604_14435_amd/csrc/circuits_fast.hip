@@ -151,24 +151,16 @@ struct PhaseSplit {
 };
 
 // One amplitude pair's share of <Z_anc> after the controlled string (phase
-// i^q times `sgn`, the permuted amplitude g) and the final H, times 2: the
-// H butterfly a0 +- a1 is applied unnormalised and the 1/2 of its two
-// 1/sqrt(2) factors is applied once to the wave's sum.
-// Two sums give the readout of both circuits of a term without the
-// butterfly: sum over pairs of z_pair2 = 4 (c S1 + d S2) with
-// S1 = sum sgn (a0r gr + a0i gi), S2 = sum sgn (a0i gr - a0r gi).
+// i^q times `sgn`, the permuted amplitude g) and the final H, applied
+// unnormalised (the two 1/sqrt(2) factors are applied once to the wave's
+// sum): |a0 + a1|^2 - |a0 - a1|^2 = 4 Re(conj(a0) a1) with a1 = sgn i^q g,
+// i^q = c + i d.  Summed over the pairs this is 4 (c S1 + d S2) with
+// S1 = sum sgn (a0r gr + a0i gi), S2 = sum sgn (a0i gr - a0r gi), which
+// serve the real and the imaginary circuit of a term alike.
 template <typename T>
 __device__ __forceinline__ void z_sums(T a0r, T a0i, T gr, T gi, T sgn, T& s1, T& s2) {
     s1 = fmat(sgn, fmat(a0r, gr, a0i * gi), s1);
     s2 = fmat(sgn, fmat(a0i, gr, -(a0r * gi)), s2);
-}
-
-template <typename T>
-__device__ __forceinline__ T z_pair2(T a0r, T a0i, T gr, T gi, const PhaseSplit<T>& ph, T sgn) {
-    const T a1r = sgn * fmat(ph.c, gr, -ph.d * gi), a1i = sgn * fmat(ph.d, gr, ph.c * gi);
-    const T b0r = a0r + a1r, b0i = a0i + a1i;
-    const T b1r = a0r - a1r, b1i = a0i - a1i;
-    return (b0r * b0r + b0i * b0i) - (b1r * b1r + b1i * b1i);
 }
 
 // <Z_anc> after applying U to the ancilla = 1 half, S^dagger (imag) and the
@@ -427,13 +419,13 @@ __device__ __forceinline__ T measure_planar_bvec(T* re, T* im, T* P, dvq_pauli p
     for (int i = 0; i < KPL; ++i) P[pad_slot(N + lane + 64 * i)] = ui[i];
     __syncthreads();
     const PhaseSplit<T> ph(sl, imag);
-    T z = 0;
+    T s1 = 0, s2 = 0;
 #pragma unroll
     for (int i = 0; i < KPL; ++i) {
         const T sgn = (__popc((unsigned)(i & sl.zh)) & 1) ? (T)-1 : (T)1;
-        z += z_pair2(a0r[i], a0i[i], gr[i], P[suffix_slot(sl, N, i)], ph, sgn);
+        z_sums(a0r[i], a0i[i], gr[i], P[suffix_slot(sl, N, i)], sgn, s1, s2);
     }
-    return (T)0.5 * wave_sum(z);
+    return (T)2 * wave_sum(fmat(ph.c, s1, ph.d * s2));
 }
 
 // Literal form: one wavefront simulates one circuit, every gate.
