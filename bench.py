@@ -57,10 +57,10 @@ CSRC = os.path.join(ROOT, "paper_2604_14435_amd", "csrc")
 MEASURED_TRAFFIC = {
     "k_terms_fast<float,10,cz,plus>": {
         "sources": ["circuits_fast.hip", "wave_state.h", "circuits.h", "common.h"],
-        "sources_sha256": "277d4200922b85ed", "fetch_kib": 201.2, "write_kib": 10902.2},
+        "sources_sha256": "277d4200922b85ed", "fetch_kib": 200.3, "write_kib": 10897.4},
     "k_fwht_fused<6,2> (n=12 dense)": {
         "sources": ["decompose.hip", "common.h"],
-        "sources_sha256": "6f82fc5f8a9e75fe", "fetch_kib": 66008.0, "write_kib": 262228.2},
+        "sources_sha256": "6f82fc5f8a9e75fe", "fetch_kib": 66123.9, "write_kib": 262227.8},
 }
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131092.6, 1.0
 
