@@ -57,7 +57,7 @@ CSRC = os.path.join(ROOT, "paper_2604_14435_amd", "csrc")
 MEASURED_TRAFFIC = {
     "k_terms_fast<float,10,cz,plus>": {
         "sources": ["circuits_fast.hip", "wave_state.h", "circuits.h", "common.h"],
-        "sources_sha256": "277d4200922b85ed", "fetch_kib": 200.3, "write_kib": 10897.4},
+        "sources_sha256": "60c7eba2c9d37357", "fetch_kib": 200.3, "write_kib": 10897.4},
     "k_fwht_fused<6,2> (n=12 dense)": {
         "sources": ["decompose.hip", "common.h"],
         "sources_sha256": "6f82fc5f8a9e75fe", "fetch_kib": 66123.9, "write_kib": 262227.8},

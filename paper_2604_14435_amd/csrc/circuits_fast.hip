@@ -39,8 +39,9 @@
 // act on the ancilla = 1 half as one permutation with phase:
 //   (U psi)[k] = omega (-1)^{Z.k} psi[k ^ X]
 // (the product of the strings, exact: the phases are powers of i), and each
-// lane forms, for its k, a0 = psi0[k], a1 = (U psi1)[k], applies S^dagger,
-// the final H and accumulates |a0'|^2 - |a1'|^2.
+// lane forms, for its k, a0 = psi0[k], a1 = (U psi1)[k]; S^dagger, the final
+// H and <Z_anc> give |a0 + a1'|^2 - |a0 - a1'|^2 (unnormalised), which the
+// kernels evaluate as 4 Re(conj(a0) a1') (z_sums, measure_planar).
 #include "circuits.h"
 #include "wave_state.h"
 
