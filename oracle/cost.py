@@ -17,7 +17,8 @@ theta <- theta - eta grad C is the optimizer of the parity trajectories.
 
 Pins: Eq. (4) route == stage-iii route, terms route == dense route, cost = 0
 at the exact solution, A = I special case, parameter shift == finite
-differences (tests/test_oracle_cost.py).
+differences, gradient descent against a quadratic whose iterates are known
+in closed form (tests/test_oracle_cost.py).
 """
 from __future__ import annotations
 

@@ -9,6 +9,11 @@ Paper:
     relative solution error of the pruned system.
 
 Solutions use LAPACK through numpy.linalg.solve.
+
+Pins: the fidelity on hand-worked values (orthogonal pair, 1/2, (24/25)^2,
+a pair orthogonal only under conjugation, global-phase invariance); the
+perturbation bound and solution errors against the paper's Section III-B
+figures (tests/test_oracle_cost.py, tests/test_oracle_pauli.py).
 """
 from __future__ import annotations
 

@@ -94,16 +94,20 @@ def test_delta_circuit_equals_dense_overlap(b_kind):
             assert abs(got - want) < 1e-14
 
 
+@pytest.mark.parametrize("ent", ["cz", "cnot"])
 @pytest.mark.parametrize("b_kind", ["plus", "vector"])
-def test_gamma_circuit_equals_dense_overlap(b_kind):
+def test_gamma_circuit_equals_dense_overlap(b_kind, ent):
+    """The gamma circuit controls V(theta) itself on the ancilla: with the
+    CNOT ladder every ladder gate becomes a doubly controlled X, so this pins
+    the controlled-controlled X against the dense permutation matrix."""
     n, layers = 3, 2
     N = 1 << n
     th = theta_uniform(n * layers, seed=6)
     b = random_unit_vector(N, seed=11) if b_kind == "vector" else np.full(N, 1 / math.sqrt(N))
-    x = ansatz_unitary_dense(th, n, layers, "cz")[:, 0]
+    x = ansatz_unitary_dense(th, n, layers, ent)[:, 0]
     for lx, lz in _strings(n, 12, 8):
         want = np.vdot(b, op.pauli_string_matrix(lx, lz, n) @ x)
-        got = qc.gamma_term(th, n, layers, "cz", (lx, lz), b_kind, b if b_kind == "vector" else None)
+        got = qc.gamma_term(th, n, layers, ent, (lx, lz), b_kind, b if b_kind == "vector" else None)
         assert abs(got - want) < 1e-14
 
 

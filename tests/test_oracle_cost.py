@@ -138,3 +138,36 @@ def test_cz_ladder_cannot_reach_fidelity_small_case():
         res = minimize(f, th0, method="BFGS", options=dict(maxiter=400))
         best = max(best, -res.fun)
     assert best < 0.995
+
+
+def test_fidelity_hand_values():
+    """F = |<u|v>|^2 of the normalised vectors (Section III-A), on cases worked
+    by hand: orthogonal states, a 45-degree pair (1/2), the pair (3,4)/(4,3)
+    whose normalised overlap is 24/25, a pair that is orthogonal only because
+    the first vector is conjugated, and invariance under a global phase."""
+    assert ola.fidelity([1.0, 0.0], [0.0, 1.0]) == 0.0
+    assert abs(ola.fidelity([1.0, 0.0], [1.0, 1.0]) - 0.5) < 1e-15
+    assert abs(ola.fidelity([3.0, 4.0], [4.0, 3.0]) - 576.0 / 625.0) < 1e-15
+    assert abs(ola.fidelity([1.0, 1j], [1.0, -1j])) < 1e-15
+    assert abs(ola.fidelity([1.0, 1j], [1.0, 1j]) - 1.0) < 1e-15
+    u = np.array([0.3, -1.2 + 0.4j, 2.0j])
+    v = np.array([1.0, 0.5j, -0.7])
+    f = ola.fidelity(u, v)
+    assert abs(ola.fidelity(np.exp(0.77j) * u, -3.0 * v) - f) < 1e-15
+    assert 0.0 < f < 1.0
+
+
+def test_gradient_descent_closed_form_quadratic():
+    """C(theta) = 1/2 sum_k a_k theta_k^2 has gradient a * theta, so gradient
+    descent gives theta_t = (1 - eta a)^t theta_0 exactly; costs[t] must be the
+    cost at thetas[t] (the iterate after t steps), for every t."""
+    a = np.array([1.0, 0.5, 2.0, 0.25])
+    th0 = np.array([1.0, -2.0, 0.5, 4.0])
+    eta, steps = 0.25, 6
+    f = lambda t: (0.5 * float(np.sum(a * t * t)), a * t)
+    thetas, costs = oc.gradient_descent(th0, f, eta, steps)
+    assert thetas.shape == (steps + 1, 4) and costs.shape == (steps + 1,)
+    for t in range(steps + 1):
+        want = (1.0 - eta * a) ** t * th0
+        assert np.max(np.abs(thetas[t] - want)) < 1e-15
+        assert abs(costs[t] - 0.5 * float(np.sum(a * want * want))) < 1e-14

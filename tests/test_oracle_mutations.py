@@ -65,3 +65,87 @@ def test_pins_catch_ry_sign_mistake():
     c, s = math.cos(t / 2), math.sin(t / 2)
     want = np.kron(np.eye(2), np.array([[c, -s], [s, c]]))[:, 0]
     assert np.allclose(good, want) and not np.allclose(bad, want)
+
+
+def test_pins_catch_ccx_control_mistake(monkeypatch):
+    """A doubly controlled X that ignores its ladder control (X on the target
+    wherever the ancilla is 1), or one with control and target of the ladder
+    gate swapped, changes the controlled V(theta) of the gamma circuit; the
+    dense-overlap pin of the CNOT-ladder gamma circuit sees both.  (Dropping
+    the ancilla control instead is harmless: the ancilla-0 half stays |0>,
+    which a CNOT leaves alone.)"""
+    n, layers = 3, 2
+    th = np.array([0.4, 1.3, -0.8, 2.1, 0.2, -1.7])
+    b = np.full(1 << n, 1 / math.sqrt(1 << n))
+    x = qc.ansatz_state(th, n, layers, "cnot")
+    l = (0b101, 0b011)
+    want = np.vdot(b, op.pauli_string_matrix(*l, n) @ x)
+    assert abs(qc.gamma_term(th, n, layers, "cnot", l) - want) < 1e-14
+
+    good = qc._apply_ccx
+
+    def ccx_ancilla_only(psi, c1, c2, t):
+        return qc.apply_controlled_1q(psi, c1, t, op.X2)
+
+    def ccx_swapped(psi, c1, c2, t):
+        return good(psi, c1, t, c2)
+
+    for bad in (ccx_ancilla_only, ccx_swapped):
+        monkeypatch.setattr(qc, "_apply_ccx", bad)
+        assert abs(qc.gamma_term(th, n, layers, "cnot", l) - want) > 1e-3
+
+
+def test_pins_catch_fidelity_mistakes():
+    """|<u|v>| without the square, or without the conjugate of u, fails the
+    hand values the fidelity pin uses."""
+    from oracle import linalg as ola
+
+    no_square = lambda u, v: float(abs(np.vdot(ola.normalized(u), ola.normalized(v))))
+    no_conj = lambda u, v: float(abs(np.sum(ola.normalized(u) * ola.normalized(v))) ** 2)
+    assert abs(ola.fidelity([1.0, 0.0], [1.0, 1.0]) - 0.5) < 1e-15
+    assert abs(no_square([1.0, 0.0], [1.0, 1.0]) - 0.5) > 0.1
+    assert abs(ola.fidelity([1.0, 1j], [1.0, -1j])) < 1e-15
+    assert abs(no_conj([1.0, 1j], [1.0, -1j])) > 0.5
+
+
+def test_pins_catch_gradient_descent_alignment_mistake():
+    """Recording the cost after the update (costs[t] = C(theta_{t+1})) breaks
+    the closed-form quadratic pin."""
+    from oracle import cost as oc
+
+    def shifted(theta0, fn, eta, steps):
+        th = np.asarray(theta0, dtype=np.float64).copy()
+        thetas, costs = [th.copy()], []
+        for _ in range(steps):
+            _, g = fn(th)
+            th = th - eta * g
+            thetas.append(th.copy())
+            costs.append(fn(th)[0])
+        costs.append(fn(th)[0])
+        return np.array(thetas), np.array(costs)
+
+    a = np.array([1.0, 0.5])
+    th0 = np.array([1.0, -2.0])
+    f = lambda t: (0.5 * float(np.sum(a * t * t)), a * t)
+    for gd, ok in ((oc.gradient_descent, True), (shifted, False)):
+        thetas, costs = gd(th0, f, 0.25, 3)
+        match = all(abs(costs[t] - 0.5 * np.sum(a * ((1 - 0.25 * a) ** t * th0) ** 2)) < 1e-14
+                    for t in range(4))
+        assert match == ok
+
+
+def test_pins_catch_global_count_mistake(monkeypatch):
+    """A global count of 2L^2 + L (one circuit per gamma term) disagrees with
+    the circuits the oracle's enumeration runs."""
+    calls = {"n": 0}
+
+    def counted(*a, **k):
+        calls["n"] += 1
+        return 0.0
+
+    for name in ("beta_circuit", "gamma_circuit"):
+        monkeypatch.setattr(qc, name, counted)
+    n, L = 3, 8
+    qc.terms(np.zeros(n), n, 1, "cz", list(range(L)), list(range(L)), "global")
+    assert calls["n"] == op.circuits_per_evaluation(n, L, "global")
+    assert calls["n"] != 2 * L * L + L

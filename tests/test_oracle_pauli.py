@@ -164,3 +164,24 @@ def test_selection_order_and_ties():
     assert list(op.select_top(C, 5)) == [0, 1, 4, 10, 15]
     assert list(op.select_tau(C, 0.25)) == [0, 1, 4]
     assert list(op.select_tau(C, 0.2499)) == [0, 1, 4, 10, 15]
+
+
+@pytest.mark.parametrize("kind,n,L", [("global", 3, 8), ("local", 3, 8), ("global", 2, 3), ("local", 2, 3)])
+def test_circuit_count_equals_enumerated_circuits(monkeypatch, kind, n, L):
+    """The count the oracle reports equals the number of Hadamard-test
+    circuits its own term enumeration runs (each complex term is a real and
+    an imaginary circuit): global 2(L^2 + L) -- 144 at n = 3, L = 8 --,
+    local 2(n+1)L^2 (Section II-B after Eq. (4))."""
+    from oracle import circuit as qc
+
+    calls = {"n": 0}
+    for name in ("beta_circuit", "delta_circuit", "gamma_circuit"):
+        def counted(*a, _f=getattr(qc, name), **k):
+            calls["n"] += 1
+            return 0.0
+        monkeypatch.setattr(qc, name, counted)
+    xs = list(range(L))
+    qc.terms(np.zeros(n), n, 1, "cz", xs, xs, kind)
+    assert calls["n"] == op.circuits_per_evaluation(n, L, kind)
+    if (kind, n, L) == ("global", 3, 8):
+        assert calls["n"] == 144
