@@ -160,3 +160,17 @@ def test_hadamard_test_identity_general_unitary():
         seen_re |= abs(want.real) > 0.05
         seen_im |= abs(want.imag) > 0.05
     assert seen_re and seen_im
+
+
+def test_pool_terms_equal_serial_terms():
+    """The process-pool runner of the full-size GPU parity test decodes its
+    flat circuit index into the same terms as the serial enumeration."""
+    import _oracle_pool
+
+    n, layers = 3, 2
+    xs = np.array([0, 1, 3, 6, 2])
+    zs = np.array([0, 2, 3, 5, 7])
+    th = theta_uniform(n * layers, seed=4)
+    wb, wd = qc.terms(th, n, layers, "cnot", xs, zs, "local")
+    gb, gd = _oracle_pool.local_terms(n, layers, "cnot", xs, zs, th, procs=2)
+    assert np.array_equal(gb, wb) and np.array_equal(gd, wd)
