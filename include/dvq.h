@@ -268,6 +268,31 @@ dvq_status dvq_vqls_grad_shift(const dvq_ansatz* ansatz, const double* theta, in
                                dvq_stream stream);
 
 /*
+ * For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same cost and
+ * gradient as dvq_vqls_grad_shift, bit for bit, with no workspace argument.
+ * Its scratch is one file-scope device array of
+ * dvq_grad_shift_noalloc_max_bytes() bytes (32 MiB) per GPU, held from the
+ * library's first use on that GPU until the process ends; the call itself
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine).
+ * The 2P + 1 shifted rows are evaluated in chunks of as many rows as fit
+ * the array.
+ *   Arguments as in dvq_vqls_grad_shift, on the device of `stream`.
+ * Errors: everything dvq_vqls_grad_shift rejects; DVQ_ECAPACITY when the
+ * 2P + 1 angle rows with their parts plus the terms of one row
+ * ((L^2 + n L^2) complex128 local, (L^2 + L) global) exceed the array.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind: calls that overlap on one GPU (different streams, or host
+ * threads) race and must be ordered by the caller.
+ */
+size_t dvq_grad_shift_noalloc_max_bytes(void);
+dvq_status dvq_vqls_grad_shift_noalloc(const dvq_ansatz* ansatz, const double* theta,
+                                       int32_t precision, const dvq_c128* coeffs,
+                                       const dvq_pauli* strings, int32_t L, int32_t b_kind,
+                                       const double* b, int32_t cost_kind, double* C,
+                                       double* grad, dvq_stream stream);
+
+/*
  * Fast path: cost and gradient by an adjoint sweep over the ansatz.  The
  * state |x> = V(theta)|0> is built gate by gate, lambda = M |x> with
  *   M = dC/dE * A^dagger U_b (sum_j Z_j) U_b^dagger A + dC/dPsi * A^dagger A  (local),

@@ -59,6 +59,9 @@ SIGNATURES = {
     "dvq_grad_shift_workspace_bytes": (c_size_t, [_A, c_int32, c_int32]),
     "dvq_vqls_grad_shift": (c_int32, [_A, _V, c_int32, _V, _V, c_int32, c_int32, _V, c_int32,
                                       _V, _V, _V, c_size_t, _V]),
+    "dvq_grad_shift_noalloc_max_bytes": (c_size_t, []),
+    "dvq_vqls_grad_shift_noalloc": (c_int32, [_A, _V, c_int32, _V, _V, c_int32, c_int32, _V, c_int32,
+                                              _V, _V, _V]),
     "dvq_vqls_grad_adjoint": (c_int32, [_A, _V, c_int32, c_int32, _V, _V, c_int32, c_int32,
                                         c_int32, _V, c_int32, _V, _V, _V]),
     "dvq_gd_step": (c_int32, [_V, _V, c_int64, c_double, _V]),

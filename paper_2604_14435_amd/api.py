@@ -273,6 +273,31 @@ def vqls_grad_shift(ansatz: AnsatzSpec, theta: torch.Tensor, coeffs: torch.Tenso
     return C, grad
 
 
+def vqls_grad_shift_noalloc(ansatz: AnsatzSpec, theta: torch.Tensor, coeffs: torch.Tensor,
+                            strings: torch.Tensor, kind: str = "local", precision: str = "f64",
+                            b_kind: str = "plus", b=None, out=None):
+    """Plain path without a workspace: (C [1], grad [P]) by the parameter-shift
+    rule, the library's per-GPU device scratch holding the intermediate terms."""
+    theta = _cuda(theta, torch.float64, "theta").reshape(-1)
+    coeffs = _cuda(coeffs, torch.complex128, "coeffs")
+    strings = _cuda(strings, torch.int32, "strings")
+    Lt = strings.shape[0]
+    _shape(theta, (ansatz.P,), "theta")
+    _shape(coeffs, (Lt,), "coeffs")
+    _shape(strings, (Lt, 2), "strings")
+    if out is None:
+        C = torch.empty(1, dtype=torch.float64, device=theta.device)
+        grad = torch.empty(ansatz.P, dtype=torch.float64, device=theta.device)
+    else:
+        C = _out(out[0], (1,), torch.float64, "C")
+        grad = _out(out[1], (ansatz.P,), torch.float64, "grad")
+    bk, bt = _b_args(b_kind, b)
+    a = ansatz.c()
+    L.call("dvq_vqls_grad_shift_noalloc", ctypes.byref(a), _p(theta), PRECISIONS[precision], _p(coeffs),
+           _p(strings), strings.shape[0], bk, _p(bt), KINDS[kind], _p(C), _p(grad), _stream(theta))
+    return C, grad
+
+
 def vqls_grad_adjoint(ansatz: AnsatzSpec, theta: torch.Tensor, coeffs: torch.Tensor,
                       strings: torch.Tensor, kind: str = "local", precision: str = "f32",
                       b_kind: str = "plus", b=None, per_row_system: bool = False, out=None):

@@ -4,6 +4,8 @@
 #include "circuits.h"
 #include "gates_lds.h"
 
+#include <mutex>
+
 namespace dvq {
 
 constexpr int kCostThreads = 1024;
@@ -160,6 +162,95 @@ k_fidelity(const double* __restrict__ theta, int n, int layers, int ent,
     if (threadIdx.x == 0) F[row] = ore * ore + oim * oim;
 }
 
+// ---------------------------------------------------------- shift rule
+
+// Memory of one shift-rule gradient: the 2P + 1 angle rows, their (N, Psi)
+// parts and costs (all rows), then the terms of `chunk` rows at a time.
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+static size_t shift_fixed_bytes(int64_t P) {
+    const int64_t R = 2 * P + 1;
+    return align256((size_t)(R * P) * sizeof(double)) + align256((size_t)R * 2 * sizeof(dvq_c128)) +
+           align256((size_t)R * sizeof(double));
+}
+
+static size_t shift_row_bytes(int n, int L, int cost_kind) {
+    const int64_t L2 = (int64_t)L * L;
+    const int64_t other = cost_kind == DVQ_COST_LOCAL ? (int64_t)n * L2 : L;
+    return (size_t)(L2 + other) * sizeof(dvq_c128);
+}
+
+// Enqueue the plain gradient: the shifted rows, then, `chunk` rows at a
+// time, every circuit of those rows and their cost, then the shift rule.
+// `mem` holds shift_fixed_bytes(P) + chunk * shift_row_bytes(n, L, kind).
+// Every argument is checked before the first launch.
+static dvq_status enqueue_shift(const dvq_ansatz* an, const double* theta, int precision,
+                                const dvq_c128* coeffs, const dvq_pauli* strings, int L, int b_kind,
+                                const double* b, int cost_kind, double* C, double* grad, char* mem,
+                                int chunk, hipStream_t s) {
+    const int P = an->n * an->layers, R = 2 * P + 1;
+    double* rows = reinterpret_cast<double*>(mem);
+    mem += align256((size_t)R * P * sizeof(double));
+    dvq_c128* parts = reinterpret_cast<dvq_c128*>(mem);
+    mem += align256((size_t)R * 2 * sizeof(dvq_c128));
+    double* crow = reinterpret_cast<double*>(mem);
+    mem += align256((size_t)R * sizeof(double));
+    dvq_c128* beta = reinterpret_cast<dvq_c128*>(mem);
+    dvq_c128* other = beta + (int64_t)chunk * L * L;
+    TermsArgs g;
+    dvq_status st = make_terms_args(g, an, rows, chunk, precision, strings, L, b_kind, b, cost_kind, beta,
+                                    other);
+    if (st != DVQ_OK) return st;
+    DVQ_REQUIRE(theta != nullptr, "theta is NULL");
+    hipLaunchKernelGGL(k_shift_rows, dim3(R), dim3(64), 0, s, theta, P, rows);
+    DVQ_CHECK_LAUNCH("k_shift_rows");
+    for (int r0 = 0; r0 < R; r0 += chunk) {
+        const int cnt = R - r0 < chunk ? R - r0 : chunk;
+        TermsArgs gc = g;
+        gc.theta = rows + (int64_t)r0 * P;
+        gc.B = cnt;
+        gc.total = gc.per_row * cnt;
+        if ((st = launch_terms(gc, precision, DVQ_EXEC_LITERAL, s)) != DVQ_OK) return st;
+        if ((st = launch_cost(coeffs, L, an->n, cost_kind, beta, other, cnt, crow + r0, parts + 2 * r0, s)) !=
+            DVQ_OK)
+            return st;
+    }
+    hipLaunchKernelGGL(k_shift_combine, dim3(1), dim3(256), 0, s, parts, P, an->n, cost_kind, crow, C, grad);
+    DVQ_CHECK_LAUNCH("k_shift_combine");
+    return DVQ_OK;
+}
+
+// Device scratch of dvq_vqls_grad_shift_noalloc: a file-scope array, one copy
+// per GPU, held until the process ends.  Host code never passes the array's
+// name to a kernel: its device address is looked up once per device with
+// hipGetSymbolAddress (that device current) and kept in scratch_addr.
+constexpr size_t kShiftScratchBytes = size_t(32) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kShiftScratchBytes];
+static std::mutex scratch_mu;
+static char* scratch_addr[kMaxDevices];
+
+// The scratch address on the device `s` belongs to.
+static dvq_status shift_scratch(hipStream_t s, char** out) {
+    int cur = 0, dev = 0;
+    DVQ_TRY_HIP(hipGetDevice(&cur));
+    dev = cur;
+    if (s != nullptr) DVQ_TRY_HIP(hipStreamGetDevice(s, &dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(DVQ_EUNSUPPORTED, "device %d >= %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (scratch_addr[dev] == nullptr) {
+        if (dev != cur) DVQ_TRY_HIP(hipSetDevice(dev));
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (dev != cur) DVQ_TRY_HIP(hipSetDevice(cur));
+        if (e != hipSuccess) return fail(DVQ_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        if (p == nullptr) return fail(DVQ_EDEVICE, "hipGetSymbolAddress(scratch) gave NULL");
+        scratch_addr[dev] = static_cast<char*>(p);
+    }
+    *out = scratch_addr[dev];
+    return DVQ_OK;
+}
+
 }  // namespace dvq
 
 using namespace dvq;
@@ -179,16 +270,9 @@ dvq_status dvq_vqls_cost(const dvq_c128* coeffs, int32_t L, int32_t n, int32_t c
 }
 
 size_t dvq_grad_shift_workspace_bytes(const dvq_ansatz* an, int32_t L, int32_t cost_kind) {
-    if (!an || an->n < 1 || an->layers < 1 || L < 1) return 0;
-    const int64_t P = (int64_t)an->n * an->layers, R = 2 * P + 1, L2 = (int64_t)L * L;
-    const int64_t other = cost_kind == DVQ_COST_LOCAL ? (int64_t)an->n * L2 : L;
-    size_t bytes = 0;
-    bytes += ((R * P * sizeof(double) + 255) / 256) * 256;                  // rows
-    bytes += ((R * L2 * sizeof(dvq_c128) + 255) / 256) * 256;               // beta
-    bytes += ((R * other * sizeof(dvq_c128) + 255) / 256) * 256;            // delta / gamma
-    bytes += ((R * 2 * sizeof(dvq_c128) + 255) / 256) * 256;                // parts
-    bytes += ((R * sizeof(double) + 255) / 256) * 256;                      // costs
-    return bytes;
+    if (!an || an->n < 1 || an->n > 13 || an->layers < 1 || an->layers > 64 || L < 1 || L > 65536) return 0;
+    const int64_t P = (int64_t)an->n * an->layers, R = 2 * P + 1;
+    return shift_fixed_bytes(P) + (size_t)R * shift_row_bytes(an->n, L, cost_kind);
 }
 
 dvq_status dvq_vqls_grad_shift(const dvq_ansatz* ansatz, const double* theta, int32_t precision,
@@ -202,35 +286,35 @@ dvq_status dvq_vqls_grad_shift(const dvq_ansatz* ansatz, const double* theta, in
     if (workspace == nullptr || workspace_bytes < need)
         return fail(DVQ_ECAPACITY, "grad_shift workspace %zu B < %zu B", workspace_bytes, need);
     const int P = ansatz->n * ansatz->layers, R = 2 * P + 1;
-    const int64_t L2 = (int64_t)L * L;
-    const int64_t other_n = cost_kind == DVQ_COST_LOCAL ? (int64_t)ansatz->n * L2 : L;
-    char* w = static_cast<char*>(workspace);
-    auto take = [&](size_t bytes) {
-        char* p = w;
-        w += ((bytes + 255) / 256) * 256;
-        return p;
-    };
-    double* rows = reinterpret_cast<double*>(take((size_t)R * P * sizeof(double)));
-    dvq_c128* beta = reinterpret_cast<dvq_c128*>(take((size_t)R * L2 * sizeof(dvq_c128)));
-    dvq_c128* other = reinterpret_cast<dvq_c128*>(take((size_t)R * other_n * sizeof(dvq_c128)));
-    dvq_c128* parts = reinterpret_cast<dvq_c128*>(take((size_t)R * 2 * sizeof(dvq_c128)));
-    double* crow = reinterpret_cast<double*>(take((size_t)R * sizeof(double)));
+    return enqueue_shift(ansatz, theta, precision, coeffs, strings, L, b_kind, b, cost_kind, C, grad,
+                         static_cast<char*>(workspace), R, stream_of(stream));
+}
 
-    TermsArgs g;
-    dvq_status st = make_terms_args(g, ansatz, rows, R, precision, strings, L, b_kind, b, cost_kind,
-                                    beta, other);
+size_t dvq_grad_shift_noalloc_max_bytes(void) { return kShiftScratchBytes; }
+
+dvq_status dvq_vqls_grad_shift_noalloc(const dvq_ansatz* ansatz, const double* theta, int32_t precision,
+                                       const dvq_c128* coeffs, const dvq_pauli* strings, int32_t L,
+                                       int32_t b_kind, const double* b, int32_t cost_kind, double* C,
+                                       double* grad, dvq_stream stream) {
+    dvq_status st = check_ansatz(ansatz, precision == DVQ_F32 ? 13 : 12);
     if (st != DVQ_OK) return st;
-    DVQ_REQUIRE(theta != nullptr, "theta is NULL");
+    DVQ_REQUIRE(coeffs && C && grad, "null device pointer");
+    DVQ_REQUIRE(L >= 1 && L <= 65536, "L=%d outside 1..65536", L);
+    const int64_t P = (int64_t)ansatz->n * ansatz->layers, R = 2 * P + 1;
+    const size_t fixed = shift_fixed_bytes(P), row = shift_row_bytes(ansatz->n, L, cost_kind);
+    if (fixed + row > kShiftScratchBytes)
+        return fail(DVQ_ECAPACITY,
+                    "grad_shift_noalloc: %zu B of shift rows + %zu B of terms per row exceed the %zu B "
+                    "device scratch (use dvq_vqls_grad_shift with a workspace)",
+                    fixed, row, kShiftScratchBytes);
+    const int64_t fit = (int64_t)((kShiftScratchBytes - fixed) / row);
+    const int chunk = (int)(fit < R ? fit : R);
     hipStream_t s = stream_of(stream);
-    hipLaunchKernelGGL(k_shift_rows, dim3(R), dim3(64), 0, s, theta, P, rows);
-    DVQ_CHECK_LAUNCH("k_shift_rows");
-    if ((st = launch_terms(g, precision, DVQ_EXEC_LITERAL, s)) != DVQ_OK) return st;
-    if ((st = launch_cost(coeffs, L, ansatz->n, cost_kind, beta, other, R, crow, parts, s)) != DVQ_OK)
-        return st;
-    hipLaunchKernelGGL(k_shift_combine, dim3(1), dim3(256), 0, s, parts, P, ansatz->n, cost_kind,
-                       crow, C, grad);
-    DVQ_CHECK_LAUNCH("k_shift_combine");
-    return DVQ_OK;
+    char* base = nullptr;
+    st = shift_scratch(s, &base);
+    if (st != DVQ_OK) return st;
+    return enqueue_shift(ansatz, theta, precision, coeffs, strings, L, b_kind, b, cost_kind, C, grad, base,
+                         chunk, s);
 }
 
 dvq_status dvq_gd_step(double* theta, const double* grad, int64_t count, double lr,

@@ -120,6 +120,15 @@ def test_grad_entry_points_reject_bad_input():
     need = lib.dvq_grad_shift_workspace_bytes(ctypes.byref(a), 8, 0)
     assert need > 0
     assert lib.dvq_vqls_grad_shift(ctypes.byref(a), d, 0, d, d, 8, 0, None, 0, d, d, d, need - 1, None) == L.DVQ_ECAPACITY
+    # the entry point without a workspace: argument and scratch-size checks
+    # come before any HIP call
+    bad = L.Ansatz(3, 0, 0)
+    assert lib.dvq_vqls_grad_shift_noalloc(ctypes.byref(bad), d, 0, d, d, 8, 0, None, 0, d, d, None) == L.DVQ_EINVAL
+    assert lib.dvq_vqls_grad_shift_noalloc(ctypes.byref(a), d, 0, d, d, 8, 0, None, 0, None, d, None) == L.DVQ_EINVAL
+    assert lib.dvq_vqls_grad_shift_noalloc(ctypes.byref(a), d, 0, d, d, 0, 0, None, 0, d, d, None) == L.DVQ_EINVAL
+    big = L.Ansatz(10, 1, 0)
+    assert lib.dvq_vqls_grad_shift_noalloc(ctypes.byref(big), d, 0, d, d, 512, 0, None, 1, d, d, None) == L.DVQ_ECAPACITY
+    assert lib.dvq_grad_shift_noalloc_max_bytes() == 32 << 20
     assert lib.dvq_gd_step(None, d, 4, 0.1, None) == L.DVQ_EINVAL
     assert lib.dvq_gd_step(d, d, -1, 0.1, None) == L.DVQ_EINVAL
 
