@@ -255,10 +255,14 @@ dvq_status dvq_vqls_cost(const dvq_c128* coeffs, int32_t L, int32_t n, int32_t c
 size_t dvq_grad_shift_workspace_bytes(const dvq_ansatz* ansatz, int32_t L, int32_t cost_kind);
 
 /*
- * Plain path: cost and exact gradient by the parameter-shift rule.  The
- * 2P + 1 rows theta, theta +/- (pi/2) e_k go through dvq_vqls_terms and the
- * aggregation; the shift rule is applied to the expectation values Psi and
- * E (or G), then the quotient rule gives dC/dtheta.
+ * Plain path: cost and exact gradient by the parameter-shift rule, the
+ * gradient that Algorithm 1 Step 4 hands to the classical optimizer (the
+ * paper's L-BFGS-B of Section III; the paper does not name its gradient
+ * method, and the shift rule is exact for RY gates).  The 2P + 1 rows
+ * theta, theta +/- (pi/2) e_k go through dvq_vqls_terms and the
+ * aggregation (Section II-C stages ii-iii); the shift rule is applied to
+ * the expectation values Psi and E (or G), then the quotient rule gives
+ * dC/dtheta.
  *   theta [P], C [1], grad [P] (float64, device).
  */
 dvq_status dvq_vqls_grad_shift(const dvq_ansatz* ansatz, const double* theta, int32_t precision,
@@ -293,7 +297,10 @@ dvq_status dvq_vqls_grad_shift_noalloc(const dvq_ansatz* ansatz, const double* t
                                        double* grad, dvq_stream stream);
 
 /*
- * Fast path: cost and gradient by an adjoint sweep over the ansatz.  The
+ * Fast path: cost and gradient by an adjoint sweep over the ansatz, the
+ * same cost (Eq. (1) global, Section II-C stage iii local) and the same
+ * gradient as dvq_vqls_grad_shift for the optimizer of Algorithm 1 Step 4,
+ * computed on one 2^n state instead of 2P + 1 evaluations.  The
  * state |x> = V(theta)|0> is built gate by gate, lambda = M |x> with
  *   M = dC/dE * A^dagger U_b (sum_j Z_j) U_b^dagger A + dC/dPsi * A^dagger A  (local),
  *   M = dC/dG * A^dagger |b><b| A + dC/dPsi * A^dagger A                     (global),
@@ -316,8 +323,10 @@ dvq_status dvq_vqls_grad_adjoint(const dvq_ansatz* ansatz, const double* theta, 
                                  int32_t b_kind, const double* b, int32_t cost_kind,
                                  double* C, double* grad, dvq_stream stream);
 
-/* theta[i] -= lr * grad[i] for i < count (the optimizer step of the
- * configured gradient descent). */
+/* theta[i] -= lr * grad[i] for i < count: a gradient-descent update of
+ * the angles, the classical update of Algorithm 1 Step 4 (the paper's own
+ * optimizer, L-BFGS-B of Section III, runs on the host over the same cost
+ * and gradient). */
 dvq_status dvq_gd_step(double* theta, const double* grad, int64_t count, double lr,
                        dvq_stream stream);
 
