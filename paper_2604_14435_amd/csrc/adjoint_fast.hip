@@ -1,5 +1,5 @@
 // Adjoint gradient with the state in registers: one wavefront per parameter
-// row (n = 10, 11; CZ ladder).  Same mathematics as k_adjoint (adjoint.hip):
+// row (n = 10, 11; CZ or CNOT ladder).  Same mathematics as k_adjoint (adjoint.hip):
 //   x = V(theta)|0>, y = A x (A = sum_l c_l P_l), Psi = <y|y>,
 //   local:  u = U_b^dag y, E = sum_k |u_k|^2 (n - 2|k|),
 //           v = dC/dE * U_b D u + dC/dPsi * y   (D = diag(n - 2|k|) = sum_j Z_j);
@@ -13,6 +13,17 @@
 // v_permlane32_swap.  Within a layer the RYs commute, so the gradient of each
 // RY may be taken before or after undoing the others of the same layer.
 // The Pauli sums and U_b are computed on natural-order copies in LDS.
+//
+// CNOT ladder.  The forward pass leaves the registers in the ladder frame
+// (stored index k holds the true amplitude of pi(k), pi the prefix parity;
+// wave_state.h).  The reverse sweep mirrors it: x and lambda are loaded in
+// that frame (x stored in frame order at the end of the forward pass,
+// lambda written in frame order by the Pauli sum), so undoing a layer's
+// ladder is a change of interpretation, not of data; the RYs a layer applied
+// in the frame are undone in the frame (ladder-paired amplitudes, the lane
+// swap for the qubit split between registers and lane bit 0), and each
+// layout swap of the forward pass that left the frame is undone by one that
+// enters it (relayout_to_ladder).
 #include "wave_state.h"
 
 namespace dvq {
@@ -68,6 +79,122 @@ __device__ __forceinline__ void grad_undo_range(T* re, T* im, int lane, const T*
         }
         grad_undo_range<T, NQ, HI, PAR, Q + 1, QEND>(re, im, lane, trig, kbase, grad);
     }
+}
+
+// Re <K_q x | lambda> for true qubit Q with the registers in the ladder
+// frame (the pairs and signs of ry_reg_ladder); lanes 0..31 hold the sum.
+template <typename T, int NQ, bool HI, int Q>
+__device__ __forceinline__ double grad_reg_ladder(const T* re, const T* im, int lane) {
+    using Ly = Lay<NQ, HI>;
+    constexpr int R = Ly::R;
+    constexpr int j = Ly::reg(Q);
+    constexpr int jp = Q + 1 < NQ ? Ly::reg(Q + 1) : -1;
+    static_assert(j >= 0 && (Q + 1 == NQ || jp >= 0), "pair not in registers");
+    constexpr int mask = (1 << j) | (jp >= 0 ? (1 << jp) : 0);
+    constexpr int low = HI ? ((1 << (Q - 5)) - 1) : ((1 << Q) - 1);
+    double acc = 0.0;
+#pragma unroll
+    for (int r0 = 0; r0 < R; ++r0) {
+        if (r0 & (1 << j)) continue;
+        const int r1 = r0 ^ mask;
+        const T l0r = other_half(re[r0]), l0i = other_half(im[r0]);
+        const T l1r = other_half(re[r1]), l1i = other_half(im[r1]);
+        // stored r0 is the true |0> member unless the qubits below Q have odd parity
+        const T v = (re[r0] * l1r + im[r0] * l1i) - (re[r1] * l0r + im[r1] * l0i);
+        acc += odd_bits(r0 & low) ? -(double)v : (double)v;
+    }
+    if constexpr (HI) {
+        if (__popc((unsigned)(lane & 31)) & 1) acc = -acc;
+    }
+    return (lane & 32) ? 0.0 : acc;
+}
+
+// For every qubit q in [Q, QEND) (register pairs in the ladder frame):
+// gradient of RY_q, then RY_q undone.
+template <typename T, int NQ, bool HI, int Q, int QEND>
+__device__ __forceinline__ void grad_undo_range_ladder(T* re, T* im, int lane, const T* trig, int kbase,
+                                                       double* __restrict__ grad) {
+    if constexpr (Q < QEND) {
+        const double gq = wave_sum(grad_reg_ladder<T, NQ, HI, Q>(re, im, lane));
+        if (lane == 0) grad[kbase + Q] = gq;
+        ry_reg_ladder<T, NQ, HI, Q>(re, im, lane, -trig[2 * (kbase + Q)], -trig[2 * (kbase + Q) + 1]);
+        grad_undo_range_ladder<T, NQ, HI, Q + 1, QEND>(re, im, lane, trig, kbase, grad);
+    }
+}
+
+// Gradient and undo of RY on true qubit RB-1 in layout LO, ladder frame:
+// the stored partner of (lane, r) is (lane ^ 1, r ^ 2^(RB-1)), and the
+// amplitude is the true |0> member iff r has even parity, so each true pair
+// is counted once, from its |0> member.
+template <typename T, int NQ>
+__device__ __forceinline__ void grad_undo_lane_ladder_lo(T* re, T* im, int lane, const T* trig, int k,
+                                                         double* __restrict__ grad) {
+    using Ly = Lay<NQ, false>;
+    constexpr int R = Ly::R, j = Ly::RB - 1;
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (odd_bits(r)) continue;
+        const int rp = r ^ (1 << j);
+        const T x1r = lane_xor1(re[rp]), x1i = lane_xor1(im[rp]);
+        const T l0r = other_half(re[r]), l0i = other_half(im[r]);
+        const T l1r = other_half(x1r), l1i = other_half(x1i);
+        const T v = (re[r] * l1r + im[r] * l1i) - (x1r * l0r + x1i * l0i);
+        acc += (double)v;
+    }
+    const double gq = wave_sum((lane & 32) ? 0.0 : acc);
+    if (lane == 0) grad[k] = gq;
+    ry_lane_ladder_lo<T, NQ>(re, im, -trig[2 * k], -trig[2 * k + 1]);
+}
+
+// Layout swap into the ladder frame, the inverse of relayout_ladder: the
+// registers (layout FROM_HI, true frame) are written to slot pi^-1(m) of
+// their true index m and read back in the other layout in natural slot
+// order, so stored index k receives the true amplitude of pi(k).  The lane
+// and register parts of pi^-1 overlap in one bit (RB for LO, 5 for HI), so
+// each write is one of two per-lane bases plus a compile-time offset.
+template <typename T, int NQ, bool FROM_HI>
+__device__ __forceinline__ void relayout_to_ladder(T* re, T* im, cplx<T>* S, int lane) {
+    using From = Lay<NQ, FROM_HI>;
+    constexpr int R = From::R;
+    constexpr int SPLIT = FROM_HI ? 5 : From::RB;
+    const int ub = ladder_unperm<NQ>(From::glane(lane));
+    const int base0 = pad_slot(ub), base1 = pad_slot(ub ^ (1 << SPLIT));
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int u = ladder_unperm<NQ>(From::greg(r));
+        const int off = u & ~(1 << SPLIT);
+        S[((u >> SPLIT) & 1 ? base1 : base0) + off + (off >> 5)] = {re[r], im[r]};
+    }
+    __syncthreads();
+    const SlotMap<NQ, !FROM_HI, kSplitSlots<T>> to(lane);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const cplx<T> v = S[to(r)];
+        re[r] = v.re;
+        im[r] = v.im;
+    }
+    __syncthreads();
+}
+
+// Lanes 0..31 (half 0), layout LO in the ladder frame, to a natural-order
+// region in the true frame: stored k goes to slot pi(k) (two bases by the
+// parity of r, as in store_state_ladder).
+template <typename T, int NQ>
+__device__ __forceinline__ void store_half0_true_lo_ladder(const T* re, const T* im, cplx<T>* S0, int lane) {
+    using Lo = Lay<NQ, false>;
+    constexpr int R = Lo::R, RB = Lo::RB;
+    constexpr int HM = ((1 << NQ) - 1) & ~((1 << RB) - 1);
+    if (!(lane & 32)) {
+        const int pl = ladder_perm<NQ>(Lo::glane(lane));
+        const int base0 = pad_slot(pl), base1 = pad_slot(pl ^ HM);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int off = ladder_perm<NQ>(r) & ((1 << RB) - 1);
+            S0[(odd_bits(r) ? base1 : base0) + off + (off >> 5)] = {re[r], im[r]};
+        }
+    }
+    __syncthreads();
 }
 
 // H on every register qubit q in [Q, QEND).
@@ -134,7 +261,9 @@ __device__ __forceinline__ void store_half0(const T* re, const T* im, cplx<T>* S
 // k = lane + 64 i the last sign splits into a per-lane and a per-i part, so
 // the coefficient carries everything but the per-i sign, and each string
 // issues 2^NQ/64 independent gathers.
-template <typename T, int NQ>
+// With FRAME, out[k] receives the sum at index pi(k) (the ladder frame):
+// sum index m is written to slot pi^-1(m).
+template <typename T, int NQ, bool FRAME = false>
 __device__ __forceinline__ void wave_pauli_sum(cplx<T>* out, const cplx<T>* in, const dvq_pauli* sp,
                                                const dvq_c128* cp, int L, bool conj_c, int lane) {
     constexpr int KPL = (1 << NQ) / 64;
@@ -156,8 +285,14 @@ __device__ __forceinline__ void wave_pauli_sum(cplx<T>* out, const cplx<T>* in, 
             ai[i] += cr * v.im + ci * v.re;
         }
     }
+    if constexpr (FRAME) {
+        const int ul = ladder_unperm<NQ>(lane);
 #pragma unroll
-    for (int i = 0; i < KPL; ++i) out[pad_slot(lane + 64 * i)] = {ar[i], ai[i]};
+        for (int i = 0; i < KPL; ++i) out[pad_slot(ul ^ ladder_unperm<NQ>(64 * i))] = {ar[i], ai[i]};
+    } else {
+#pragma unroll
+        for (int i = 0; i < KPL; ++i) out[pad_slot(lane + 64 * i)] = {ar[i], ai[i]};
+    }
     __syncthreads();
 }
 
@@ -187,16 +322,17 @@ __device__ __forceinline__ void wave_householder(cplx<T>* v, const double* __res
     __syncthreads();
 }
 
-template <typename T, int NQ>
+template <typename T, int NQ, int ENT>
 __host__ __device__ constexpr size_t wave_adjoint_lds(int layers, int L) {
     constexpr int N = 1 << NQ;
+    constexpr int regions = ENT == DVQ_ENT_CZ_LADDER ? 3 : 4;    // x, y/lambda, v (+ x in the ladder frame)
     return (size_t)(2 * N + (2 * N) / 32) * sizeof(cplx<T>)      // scratch for layout swaps
-           + 3 * (size_t)(N + N / 32) * sizeof(cplx<T>)          // x, y/lambda, v
+           + regions * (size_t)(N + N / 32) * sizeof(cplx<T>)
            + (size_t)L * (sizeof(dvq_pauli) + sizeof(dvq_c128))  // strings, coeffs
            + (size_t)2 * NQ * layers * sizeof(T);                // rotation table
 }
 
-template <typename T, int NQ>
+template <typename T, int NQ, int ENT>
 __global__ void __launch_bounds__(64)
 k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __restrict__ coeffs,
                const dvq_pauli* __restrict__ strings, int L, int per_row_system, int bkind,
@@ -210,7 +346,9 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
     cplx<T>* RX = S + (2 * N + (2 * N) / 32);
     cplx<T>* RY = RX + N1;
     cplx<T>* RV = RY + N1;
-    dvq_pauli* sp = reinterpret_cast<dvq_pauli*>(RV + N1);
+    constexpr bool CNOT = ENT == DVQ_ENT_CNOT_LADDER;
+    cplx<T>* RXF = RV + N1;  // x in the ladder frame (CNOT ladder only)
+    dvq_pauli* sp = reinterpret_cast<dvq_pauli*>(CNOT ? RXF + N1 : RV + N1);
     dvq_c128* cp = reinterpret_cast<dvq_c128*>(sp + L);
     T* trig = reinterpret_cast<T*>(cp + L);
     const int lane = threadIdx.x;
@@ -230,12 +368,25 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
         re[r] = (r == 0 && (lane & 31) == 0) ? (T)1 : (T)0;
         im[r] = (T)0;
     }
-    forward_layers<T, NQ>(re, im, S, trig, layers, lane);
     const int pf = layers & 1;
-    if (pf)
-        store_half0<T, NQ, true>(re, im, RX, lane, 1);
-    else
-        store_half0<T, NQ, false>(re, im, RX, lane, 0);
+    if constexpr (!CNOT) {
+        forward_layers<T, NQ>(re, im, S, trig, layers, lane);
+        if (pf)
+            store_half0<T, NQ, true>(re, im, RX, lane, 1);
+        else
+            store_half0<T, NQ, false>(re, im, RX, lane, 0);
+    } else {
+        // ends in the ladder frame, layout HI for an odd layer count
+        forward_layers_ladder<T, NQ>(re, im, S, trig, layers, lane);
+        if (pf) {
+            store_half0<T, NQ, true>(re, im, RXF, lane, 0);
+            relayout_ladder<T, NQ, true>(re, im, S, lane);  // -> LO, true frame
+            store_half0<T, NQ, false>(re, im, RX, lane, 0);
+        } else {
+            store_half0<T, NQ, false>(re, im, RXF, lane, 0);
+            store_half0_true_lo_ladder<T, NQ>(re, im, RX, lane);
+        }
+    }
 
     // y = A x, Psi = <y|y>
     wave_pauli_sum<T, NQ>(RY, RX, sp, cp, L, false, lane);
@@ -316,11 +467,41 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
         }
         __syncthreads();
     }
-    // lambda = A^dag v -> RY
-    wave_pauli_sum<T, NQ>(RY, RV, sp, cp, L, true, lane);
+    // lambda = A^dag v -> RY (in the ladder frame for the CNOT ladder)
+    wave_pauli_sum<T, NQ, CNOT>(RY, RV, sp, cp, L, true, lane);
 
     // reverse sweep: x in lanes 0..31, lambda in lanes 32..63
     double* g = grad + row * P;
+    if constexpr (CNOT) {
+        constexpr int RB = Lay<NQ, false>::RB;
+        if (pf)
+            load_halves<T, NQ, true>(re, im, RXF, RY, lane, 0);
+        else
+            load_halves<T, NQ, false>(re, im, RXF, RY, lane, 0);
+        for (int l = layers - 1; l >= 1; --l) {
+            const int kb = l * NQ;
+            if (l & 1) {
+                // odd layer (forward: HI qubits in the frame, swap to LO,
+                // LO qubits 0..4): starts in LO, true state of its RYs
+                grad_undo_range<T, NQ, false, 0, 0, 5>(re, im, lane, trig, kb, g);
+                relayout_to_ladder<T, NQ, false>(re, im, S, lane);
+                grad_undo_range_ladder<T, NQ, true, 5, NQ>(re, im, lane, trig, kb, g);
+            } else {
+                // even layer >= 2 (forward: LO qubits 0..RB-1 in the frame,
+                // swap to HI, HI qubits 5..NQ-1): starts in HI
+                grad_undo_range<T, NQ, true, 0, 5, NQ>(re, im, lane, trig, kb, g);
+                relayout_to_ladder<T, NQ, true>(re, im, S, lane);
+                if constexpr (RB - 1 < 5) grad_undo_lane_ladder_lo<T, NQ>(re, im, lane, trig, kb + RB - 1, g);
+                grad_undo_range_ladder<T, NQ, false, 0, RB - 1>(re, im, lane, trig, kb, g);
+            }
+        }
+        // layer 0 (forward: LO qubits, plain swap, HI qubits RB..NQ-1): starts in HI
+        grad_undo_range<T, NQ, true, 0, RB, NQ>(re, im, lane, trig, 0, g);
+        relayout<T, NQ, true>(re, im, S, lane);
+        grad_undo_range<T, NQ, false, 0, 0, NQ>(re, im, lane, trig, 0, g);
+        if (lane == 0) Cout[row] = cost;
+        return;
+    }
     int l = layers - 1;
     if (pf) {
         // last layer even-indexed: ended in HI with p = 1 after its ladder
@@ -345,18 +526,30 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
     if (lane == 0) Cout[row] = cost;
 }
 
+template <typename T, int NQ, int ENT>
+static dvq_status launch_adjoint_wave_ent(const dvq_ansatz* an, const double* theta, int B,
+                                          const dvq_c128* coeffs, const dvq_pauli* strings, int L,
+                                          int per_row_system, int bkind, const double* b, int kind,
+                                          double* C, double* grad, hipStream_t s) {
+    const size_t lds = wave_adjoint_lds<T, NQ, ENT>(an->layers, L);
+    if (lds > kMaxLdsBytes) return DVQ_EUNSUPPORTED;
+    DVQ_TRY_HIP(allow_lds((const void*)k_adjoint_wave<T, NQ, ENT>, lds));
+    hipLaunchKernelGGL((k_adjoint_wave<T, NQ, ENT>), dim3(B), dim3(64), lds, s, theta, an->layers, coeffs,
+                       strings, L, per_row_system, bkind, b, kind, C, grad);
+    DVQ_CHECK_LAUNCH("k_adjoint_wave");
+    return DVQ_OK;
+}
+
 template <typename T, int NQ>
 static dvq_status launch_adjoint_wave(const dvq_ansatz* an, const double* theta, int B,
                                       const dvq_c128* coeffs, const dvq_pauli* strings, int L,
                                       int per_row_system, int bkind, const double* b, int kind,
                                       double* C, double* grad, hipStream_t s) {
-    const size_t lds = wave_adjoint_lds<T, NQ>(an->layers, L);
-    if (lds > kMaxLdsBytes) return DVQ_EUNSUPPORTED;
-    DVQ_TRY_HIP(allow_lds((const void*)k_adjoint_wave<T, NQ>, lds));
-    hipLaunchKernelGGL((k_adjoint_wave<T, NQ>), dim3(B), dim3(64), lds, s, theta, an->layers, coeffs,
-                       strings, L, per_row_system, bkind, b, kind, C, grad);
-    DVQ_CHECK_LAUNCH("k_adjoint_wave");
-    return DVQ_OK;
+    if (an->entangler == DVQ_ENT_CZ_LADDER)
+        return launch_adjoint_wave_ent<T, NQ, DVQ_ENT_CZ_LADDER>(an, theta, B, coeffs, strings, L, per_row_system,
+                                                                 bkind, b, kind, C, grad, s);
+    return launch_adjoint_wave_ent<T, NQ, DVQ_ENT_CNOT_LADDER>(an, theta, B, coeffs, strings, L, per_row_system,
+                                                               bkind, b, kind, C, grad, s);
 }
 
 // Dispatch for the register-resident adjoint; DVQ_EUNSUPPORTED when the
@@ -365,7 +558,7 @@ dvq_status launch_adjoint_fast(const dvq_ansatz* an, const double* theta, int B,
                                const dvq_c128* coeffs, const dvq_pauli* strings, int L,
                                int per_row_system, int bkind, const double* b, int kind, double* C,
                                double* grad, hipStream_t s) {
-    if (an->entangler != DVQ_ENT_CZ_LADDER || an->n * an->layers > 1024) return DVQ_EUNSUPPORTED;
+    if (an->n * an->layers > 1024) return DVQ_EUNSUPPORTED;
     if (precision == DVQ_F32) {
         if (an->n == 10)
             return launch_adjoint_wave<float, 10>(an, theta, B, coeffs, strings, L, per_row_system, bkind, b,

@@ -188,18 +188,21 @@ def test_adjoint_autograd_function():
     assert np.max(np.abs(th.grad.cpu().numpy() - 2 * g0)) < 1e-10
 
 
+@pytest.mark.parametrize("ent", ["cz", "cnot"])
 @pytest.mark.parametrize("n,layers,kind,b_kind,precision", [
     (10, 3, "local", "vector", "f64"), (10, 5, "global", "plus", "f32"),
     (10, 2, "global", "vector", "f64"), (10, 1, "local", "plus", "f64"),
-    (11, 2, "local", "plus", "f32"), (11, 3, "global", "vector", "f32")])
-def test_register_adjoint_shapes(n, layers, kind, b_kind, precision):
-    """The wavefront adjoint (n = 10, 11, CZ ladder): both cost kinds, both
-    state preparations, odd and even depths; vs the exact shift rule."""
+    (10, 4, "local", "plus", "f32"), (10, 6, "global", "plus", "f64"),
+    (11, 2, "local", "plus", "f32"), (11, 3, "global", "vector", "f32"),
+    (11, 4, "local", "vector", "f32"), (11, 1, "global", "plus", "f32")])
+def test_register_adjoint_shapes(ent, n, layers, kind, b_kind, precision):
+    """The wavefront adjoint (n = 10, 11, both ladders): both cost kinds,
+    both state preparations, odd and even depths; vs the exact shift rule."""
     A, At, c, xs, zs, strings = _system(n, 1.0, -0.4, top_L=12)
     b = random_unit_vector(1 << n, seed=n + layers) if b_kind == "vector" else None
     th = theta_uniform(n * layers, seed=layers)
-    an = api.AnsatzSpec(n, layers, "cz")
-    parts = lambda t: oc.parts_theta_dense(t, At, n, layers, "cz", kind, b_kind, b)
+    an = api.AnsatzSpec(n, layers, ent)
+    parts = lambda t: oc.parts_theta_dense(t, At, n, layers, ent, kind, b_kind, b)
     C0, g0 = oc.grad_parameter_shift(parts, th, n, kind)
     C, g = api.vqls_grad_adjoint(an, _gpu(th), _gpu(c), _gpu(strings), kind, precision, b_kind,
                                  None if b is None else _gpu(b))
@@ -208,19 +211,38 @@ def test_register_adjoint_shapes(n, layers, kind, b_kind, precision):
     assert np.max(np.abs(g[0].cpu().numpy() - g0)) < tol_g
 
 
-def test_register_adjoint_per_row_batch():
+@pytest.mark.parametrize("ent", ["cz", "cnot"])
+def test_register_adjoint_per_row_batch(ent):
     """B = 5 rows with their own systems at n = 10 (the warm-start data path)."""
     n, layers = 10, 4
     rows = [_system(n, a, b, top_L=16) for a, b in [(1.0, -0.3), (0.9, -0.45), (1.2, -0.1), (0.8, -0.2), (1.1, -0.49)]]
     coeffs = np.stack([r[2] for r in rows])
     strings = np.stack([r[5] for r in rows])
     th = theta_uniform(5 * n * layers, seed=9).reshape(5, -1)
-    an = api.AnsatzSpec(n, layers, "cz")
+    an = api.AnsatzSpec(n, layers, ent)
     C, g = api.vqls_grad_adjoint(an, _gpu(th), _gpu(coeffs), _gpu(strings), "local", "f64",
                                  per_row_system=True)
     for r in range(5):
         At = rows[r][1]
-        parts = lambda t: oc.parts_theta_dense(t, At, n, layers, "cz", "local")
+        parts = lambda t: oc.parts_theta_dense(t, At, n, layers, ent, "local")
         C0, g0 = oc.grad_parameter_shift(parts, th[r], n, "local")
         assert abs(C[r].item() - C0) < 1e-12
         assert np.max(np.abs(g[r].cpu().numpy() - g0)) < 1e-10
+
+
+@pytest.mark.parametrize("layers", [4, 6])
+def test_register_adjoint_cnot_bench_system(layers):
+    """The bench system (n = 10, L = 64) with the RY + CNOT ladder, the
+    ansatz of the fidelity runs: complex64 and complex128 register adjoints
+    against the exact shift rule on the dense cost, both cost kinds."""
+    n = 10
+    A, At, c, xs, zs, strings = _system(n, 1.0, -0.45, tau=0.01)
+    th = theta_uniform(n * layers, seed=11)
+    an = api.AnsatzSpec(n, layers, "cnot")
+    for kind in ("local", "global"):
+        parts = lambda t: oc.parts_theta_dense(t, At, n, layers, "cnot", kind)
+        C0, g0 = oc.grad_parameter_shift(parts, th, n, kind)
+        for precision, tol_c, tol_g in (("f64", 1e-12, 1e-10), ("f32", 1e-6, 1e-5)):
+            C, g = api.vqls_grad_adjoint(an, _gpu(th), _gpu(c), _gpu(strings), kind, precision)
+            assert abs(C.item() - C0) < tol_c, (kind, precision)
+            assert np.max(np.abs(g[0].cpu().numpy() - g0)) < tol_g, (kind, precision)
