@@ -116,9 +116,10 @@ class Evaluator:
 
 
 def lbfgs(evaluate, theta0: np.ndarray, max_evals: int = 2000, target: float | None = None,
-          gtol: float = 1e-9, ftol: float = 1e-15, memory: int = 10) -> tuple[np.ndarray, Trace]:
+          gtol: float = 1e-9, ftol: float = 1e-15, memory: int = 10, stop_when=None) -> tuple[np.ndarray, Trace]:
     """Minimise with L-BFGS-B from theta0.  Stops at convergence, after
-    `max_evals` evaluations, or as soon as an evaluated cost is <= target."""
+    `max_evals` evaluations, as soon as an evaluated cost is <= target, or
+    as soon as ``stop_when(theta)`` is true for an accepted iterate."""
     from scipy.optimize import minimize
 
     tr = Trace()
@@ -143,6 +144,8 @@ def lbfgs(evaluate, theta0: np.ndarray, max_evals: int = 2000, target: float | N
         tr.thetas.append(np.array(xk))
         tr.iter_evals.append(tr.evals)
         tr.iter_seconds.append(time.perf_counter() - t0)
+        if stop_when is not None and stop_when(xk):
+            raise _Reached()
 
     try:
         res = minimize(fun, np.asarray(theta0, dtype=np.float64), jac=True, method="L-BFGS-B",
@@ -174,3 +177,108 @@ def lbfgs_refine(fast, precise, theta0: np.ndarray, max_evals: int = 4000, targe
                stop=f"float32: {t1.stop[:40]}; float64: {t2.stop[:40]}")
     return (th2 if min(t2.costs, default=np.inf) <= min(t1.costs) else th1), tr
 
+
+
+class BatchEvaluator:
+    """Cost and gradient of B rows, row r with its own system (coeffs [B, L],
+    strings [B, L, 2]), from one adjoint launch per call (complex64 or
+    complex128 states); host arrays in, host arrays out."""
+
+    def __init__(self, ansatz: api.AnsatzSpec, coeffs: torch.Tensor, strings: torch.Tensor,
+                 precision: str = "f64", kind: str = "local"):
+        self.an, self.coeffs, self.strings = ansatz, coeffs, strings
+        self.precision, self.kind = precision, kind
+        dev = coeffs.device
+        B, P = coeffs.shape[0], ansatz.P
+        self.theta = torch.empty((B, P), dtype=torch.float64, device=dev)
+        self.theta_host = torch.empty((B, P), dtype=torch.float64, pin_memory=True)
+        self.packed = torch.empty((B, P + 1), dtype=torch.float64, device=dev)
+        self.out_host = torch.empty((B, P + 1), dtype=torch.float64, pin_memory=True)
+        self.C = torch.empty(B, dtype=torch.float64, device=dev)
+        self.g = torch.empty((B, P), dtype=torch.float64, device=dev)
+        self.evals = 0
+
+    def __call__(self, theta: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+        self.theta_host.numpy()[:] = theta
+        self.theta.copy_(self.theta_host, non_blocking=True)
+        api.vqls_grad_adjoint(self.an, self.theta, self.coeffs, self.strings, self.kind, self.precision,
+                              per_row_system=True, out=(self.C, self.g))
+        self.packed[:, 0].copy_(self.C)
+        self.packed[:, 1:].copy_(self.g)
+        self.out_host.copy_(self.packed)  # synchronous
+        self.evals += 1
+        v = self.out_host.numpy()
+        return v[:, 0].copy(), v[:, 1:].copy()
+
+
+def lbfgs_batched(evaluate, theta0: np.ndarray, iters: int = 300, memory: int = 10, c1: float = 1e-4,
+                  max_backtracks: int = 20) -> tuple[np.ndarray, np.ndarray]:
+    """B independent L-BFGS minimisations advanced together (host-side, as
+    the paper's optimizer), each row with its own curvature pairs and its own
+    Armijo backtracking step; every call of ``evaluate(theta [B, P]) ->
+    (C [B], grad [B, P])`` evaluates all rows at once, rows not searching a
+    step being evaluated at their current point.  A row whose direction is
+    not a descent direction restarts from the gradient with an empty memory;
+    pairs with s.y <= 0 are not stored.  Returns (theta [B, P], C [B])."""
+    x = np.array(theta0, dtype=np.float64, copy=True)
+    B, P = x.shape
+    f, g = evaluate(x)
+    S = np.zeros((memory, B, P))
+    Y = np.zeros((memory, B, P))
+    rho = np.zeros((memory, B))
+    count = np.zeros(B, dtype=np.int64)  # stored pairs per row (ring buffer, newest at count-1)
+    for _ in range(iters):
+        # two-loop recursion, every row with its own pairs (empty slots have rho = 0)
+        q = -g.copy()
+        alpha = np.zeros((memory, B))
+        for back in range(memory):
+            slot = (count - 1 - back) % memory
+            valid = back < np.minimum(count, memory)
+            s_k, y_k, r_k = S[slot, np.arange(B)], Y[slot, np.arange(B)], rho[slot, np.arange(B)] * valid
+            alpha[back] = r_k * np.einsum("bp,bp->b", s_k, q)
+            q -= alpha[back][:, None] * y_k
+        last = (count - 1) % memory
+        s_l, y_l = S[last, np.arange(B)], Y[last, np.arange(B)]
+        yy = np.einsum("bp,bp->b", y_l, y_l)
+        gamma = np.where(count > 0, np.einsum("bp,bp->b", s_l, y_l) / np.where(yy > 0, yy, 1.0), 1.0)
+        q *= gamma[:, None]
+        for back in reversed(range(memory)):
+            slot = (count - 1 - back) % memory
+            valid = back < np.minimum(count, memory)
+            s_k, y_k, r_k = S[slot, np.arange(B)], Y[slot, np.arange(B)], rho[slot, np.arange(B)] * valid
+            beta = r_k * np.einsum("bp,bp->b", y_k, q)
+            q += (alpha[back] - beta)[:, None] * s_k
+        d = q
+        gd = np.einsum("bp,bp->b", g, d)
+        bad = gd >= 0
+        if bad.any():  # restart those rows from steepest descent
+            d[bad] = -g[bad]
+            gd[bad] = -np.einsum("bp,bp->b", g[bad], g[bad])
+            count[bad] = 0
+        gnorm = np.sqrt(np.einsum("bp,bp->b", g, g))
+        t = np.where(count > 0, 1.0, np.minimum(1.0, 1.0 / np.maximum(gnorm, 1e-300)))
+        pending = gd < 0
+        x_new, f_new, g_new = x.copy(), f.copy(), g.copy()
+        for _ls in range(max_backtracks):
+            if not pending.any():
+                break
+            trial = np.where(pending[:, None], x + t[:, None] * d, x)
+            ft, gt = evaluate(trial)
+            ok = pending & (ft <= f + c1 * t * gd)
+            x_new[ok], f_new[ok], g_new[ok] = trial[ok], ft[ok], gt[ok]
+            pending &= ~ok
+            t = np.where(pending, 0.5 * t, t)
+        accepted = ~pending & (gd < 0)
+        s = x_new - x
+        y = g_new - g
+        sy = np.einsum("bp,bp->b", s, y)
+        store = accepted & (sy > 1e-300)
+        slot = count % memory
+        rows = np.nonzero(store)[0]
+        S[slot[rows], rows] = s[rows]
+        Y[slot[rows], rows] = y[rows]
+        rho[slot[rows], rows] = 1.0 / sy[rows]
+        count[rows] += 1
+        count[pending] = 0  # no acceptable step: restart that row's memory
+        x, f, g = x_new, f_new, g_new
+    return x, f
