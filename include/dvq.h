@@ -374,6 +374,51 @@ dvq_status dvq_adamw_step(float* params, const float* grads, float* m, float* v,
                           int32_t t, float lr, float beta1, float beta2, float eps,
                           float weight_decay, dvq_stream stream);
 
+/*
+ * Fused forms of the warm-start network (hidden 64, 128 or 256, d_in <= 32,
+ * d_out <= 128; DVQ_EUNSUPPORTED otherwise).  The same arithmetic as
+ * dvq_mlp_forward / _loss_grad / _backward / dvq_adamw_step (bfloat16 GEMM
+ * operands, float32 accumulation, bias gradients on the unrounded float32
+ * values), computed per chunk of 32 batch rows with the chunk's
+ * activations kept on chip.
+ *
+ * Input standardisation: with feat_mean and feat_inv_std (both [d_in],
+ * device, or both NULL), x is replaced by (x - mean) * inv_std before the
+ * first layer.
+ */
+
+/* Column mean and 1 / standard deviation (n - 1 denominator, standard
+ * deviation at least 1e-12) of X [rows][d] float32; sums in float64. */
+dvq_status dvq_feature_stats(const float* X, int32_t rows, int32_t d, float* mean, float* inv_std,
+                             dvq_stream stream);
+
+/* Y [batch][d_out] = the network on X [batch][d_in], one launch. */
+dvq_status dvq_mlp_predict(const dvq_mlp_shape* shape, const float* params, const float* X, int32_t batch,
+                           const float* feat_mean, const float* feat_inv_std, float* Y, dvq_stream stream);
+
+/* Scratch bytes for dvq_mlp_train_step: one partial gradient per chunk of
+ * 32 rows plus one loss sum per chunk. */
+size_t dvq_mlp_train_workspace_bytes(const dvq_mlp_shape* shape, int32_t batch);
+
+/*
+ * One training step on a minibatch: the rows rows[0..batch-1] of
+ * X [x_rows][d_in] and of the target angles T [x_rows][d_out] (rows = NULL:
+ * rows 0..batch-1, batch <= x_rows); an index outside 0..x_rows-1
+ * contributes no loss and no gradient (the mean still divides by
+ * batch * d_out),
+ * loss mean(1 - cos(Y - T)), its gradient, and one AdamW step
+ * (t >= 1 counts steps) on params, m, v in place.
+ *   grads [param_count] receives the gradient (may be NULL).
+ *   loss  [1] float64 receives the minibatch loss before the step (may be NULL).
+ * Two launches: the chunks' forward and backward passes, then the
+ * chunk-ordered sum of their gradients with the AdamW update.
+ */
+dvq_status dvq_mlp_train_step(const dvq_mlp_shape* shape, float* params, float* m, float* v, int32_t t,
+                              float lr, float beta1, float beta2, float eps, float weight_decay,
+                              const float* X, const float* T, int32_t x_rows, const int32_t* rows,
+                              int32_t batch, const float* feat_mean, const float* feat_inv_std, float* grads,
+                              double* loss, void* workspace, size_t workspace_bytes, dvq_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -73,6 +73,11 @@ SIGNATURES = {
     "dvq_mlp_backward": (c_int32, [_M, _V, _V, _V, _V, _V, c_int32, _V, _V, c_size_t, _V]),
     "dvq_adamw_step": (c_int32, [_V, _V, _V, _V, c_int64, c_int32, c_float, c_float, c_float,
                                  c_float, c_float, _V]),
+    "dvq_feature_stats": (c_int32, [_V, c_int32, c_int32, _V, _V, _V]),
+    "dvq_mlp_predict": (c_int32, [_M, _V, _V, c_int32, _V, _V, _V, _V]),
+    "dvq_mlp_train_workspace_bytes": (c_size_t, [_M, c_int32]),
+    "dvq_mlp_train_step": (c_int32, [_M, _V, _V, _V, c_int32, c_float, c_float, c_float, c_float, c_float,
+                                     _V, _V, c_int32, _V, c_int32, _V, _V, _V, _V, _V, c_size_t, _V]),
 }
 
 _lib = None

@@ -442,3 +442,88 @@ def adamw_step(params, grads, m, v, t: int, lr: float = 1e-3, beta1: float = 0.9
     grads = _shape(_cuda(grads, torch.float32, "grads"), tuple(params.shape), "grads")
     L.call("dvq_adamw_step", _p(params), _p(grads), _p(m), _p(v), params.numel(), int(t), float(lr),
            float(beta1), float(beta2), float(eps), float(weight_decay), _stream(params))
+
+
+def feature_stats(X: torch.Tensor, out=None):
+    """(mean [d], 1/std [d]) float32 of the rows of X [rows, d] (n - 1 denominator)."""
+    X = _cuda(X, torch.float32, "X")
+    if X.dim() != 2:
+        raise ValueError(f"X must be [rows, d], got {tuple(X.shape)}")
+    d = X.shape[1]
+    if out is None:
+        mean = torch.empty(d, dtype=torch.float32, device=X.device)
+        isd = torch.empty(d, dtype=torch.float32, device=X.device)
+    else:
+        mean = _out(out[0], (d,), torch.float32, "mean")
+        isd = _out(out[1], (d,), torch.float32, "inv_std")
+    L.call("dvq_feature_stats", _p(X), X.shape[0], d, _p(mean), _p(isd), _stream(X))
+    return mean, isd
+
+
+def _stats_args(stats, d_in: int):
+    if stats is None:
+        return None, None
+    mean, isd = (_cuda(t, torch.float32, nm) for t, nm in ((stats[0], "mean"), (stats[1], "inv_std")))
+    _shape(mean, (d_in,), "mean")
+    _shape(isd, (d_in,), "inv_std")
+    return mean, isd
+
+
+def mlp_predict(shape: L.MlpShape, params: torch.Tensor, X: torch.Tensor, stats=None, out=None):
+    """Y [batch, d_out] float32 from one fused launch; `stats` = (mean, 1/std)
+    standardises the inputs on the device."""
+    params = _cuda(params, torch.float32, "params")
+    X = _cuda(X, torch.float32, "X")
+    B = X.shape[0]
+    _shape(params, (mlp_param_count(shape),), "params")
+    _shape(X, (B, shape.d_in), "X")
+    mean, isd = _stats_args(stats, shape.d_in)
+    Y = torch.empty((B, shape.d_out), dtype=torch.float32, device=X.device) if out is None else \
+        _out(out, (B, shape.d_out), torch.float32, "Y")
+    L.call("dvq_mlp_predict", ctypes.byref(shape), _p(params), _p(X), B, _p(mean), _p(isd), _p(Y), _stream(X))
+    return Y
+
+
+class TrainWorkspace:
+    """Scratch memory of dvq_mlp_train_step for a batch size, allocated once."""
+
+    def __init__(self, shape: L.MlpShape, batch: int, device):
+        nbytes = L.load().dvq_mlp_train_workspace_bytes(ctypes.byref(shape), batch)
+        self.batch = batch
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def mlp_train_step(shape: L.MlpShape, params, m, v, t: int, X, T, rows=None, batch: int | None = None,
+                   stats=None, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+                   weight_decay: float = 0.0, workspace: TrainWorkspace | None = None, loss=None, grads=None):
+    """One fused training step (forward, loss, backward, AdamW) on the rows
+    `rows` (int32 [batch], device) of X [*, d_in] and T [*, d_out]; params,
+    m, v updated in place.  `loss` ([1] float64) and `grads` (packed like
+    params) receive the minibatch loss and gradient when given."""
+    n_par = mlp_param_count(shape)
+    params, m, v = (_out(x, (n_par,), torch.float32, nm) for x, nm in ((params, "params"), (m, "m"), (v, "v")))
+    X = _cuda(X, torch.float32, "X")
+    T = _cuda(T, torch.float32, "T")
+    if X.dim() != 2 or X.shape[1] != shape.d_in:
+        raise ValueError(f"X must be [*, {shape.d_in}], got {tuple(X.shape)}")
+    _shape(T, (X.shape[0], shape.d_out), "T")
+    if rows is not None:
+        rows = _cuda(rows, torch.int32, "rows")
+        if rows.dim() != 1:
+            raise ValueError("rows must be 1-D")
+        batch = rows.shape[0]
+    elif batch is None:
+        batch = X.shape[0]
+    if batch > X.shape[0] and rows is None:
+        raise ValueError(f"batch {batch} > rows of X {X.shape[0]}")
+    mean, isd = _stats_args(stats, shape.d_in)
+    if workspace is None or workspace.batch < batch:
+        workspace = TrainWorkspace(shape, batch, X.device)
+    if loss is not None:
+        loss = _out(loss, (1,), torch.float64, "loss")
+    if grads is not None:
+        grads = _out(grads, (n_par,), torch.float32, "grads")
+    L.call("dvq_mlp_train_step", ctypes.byref(shape), _p(params), _p(m), _p(v), int(t), float(lr), float(beta1),
+           float(beta2), float(eps), float(weight_decay), _p(X), _p(T), X.shape[0], _p(rows), int(batch), _p(mean), _p(isd),
+           _p(grads), _p(loss), _p(workspace.buf), workspace.buf.numel(), _stream(X))
+    return workspace

@@ -31,6 +31,7 @@ SOURCES = [
     "adjoint.hip",
     "adjoint_fast.hip",
     "mlp.hip",
+    "mlp_fused.hip",
 ]
 
 DEVICE_FLAGS = [

@@ -10,18 +10,9 @@
 // One generic kernel covers all eight GEMMs of a training step: operands are
 // addressed through (row, column) strides, so transposed operands need no
 // copies.  Each wavefront computes one 16 x 16 output tile.
-#include "common.h"
+#include "mlp_common.h"
 
 namespace dvq {
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ __bf16 to_bf16(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return __builtin_bit_cast(__bf16, (unsigned short)(u >> 16));
-}
 
 struct GemmArgs {
     int M, N, K;
@@ -61,7 +52,7 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
     bf16x8 a, b;
     load(0, a, b);
     for (int k0 = 0; k0 < g.K; k0 += 32) {
-        bf16x8 an, bn;
+        bf16x8 an = a, bn = b;
         if (k0 + 32 < g.K) load(k0 + 32, an, bn);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
         a = an;
@@ -148,32 +139,6 @@ __global__ void k_adamw(float* __restrict__ p, const float* __restrict__ g, floa
         const float mh = mi / c1, vh = vi / c2;
         p[i] -= lr * (mh / (sqrtf(vh) + eps) + wd * p[i]);
     }
-}
-
-struct MlpOffsets {
-    int64_t W1, b1, W2, b2, W3, b3, total;
-};
-
-static MlpOffsets offsets(const dvq_mlp_shape& s) {
-    MlpOffsets o;
-    o.W1 = 0;
-    o.b1 = o.W1 + (int64_t)s.hidden * s.d_in;
-    o.W2 = o.b1 + s.hidden;
-    o.b2 = o.W2 + (int64_t)s.hidden * s.hidden;
-    o.W3 = o.b2 + s.hidden;
-    o.b3 = o.W3 + (int64_t)s.d_out * s.hidden;
-    o.total = o.b3 + s.d_out;
-    return o;
-}
-
-static dvq_status check_shape(const dvq_mlp_shape* s, int batch) {
-    DVQ_REQUIRE(s != nullptr, "shape is NULL");
-    DVQ_REQUIRE(s->d_in >= 1 && s->d_in <= 64, "d_in=%d outside 1..64", s->d_in);
-    DVQ_REQUIRE(s->hidden >= 32 && s->hidden <= 512 && s->hidden % 32 == 0,
-                "hidden=%d must be a multiple of 32 in 32..512", s->hidden);
-    DVQ_REQUIRE(s->d_out >= 1 && s->d_out <= 512, "d_out=%d outside 1..512", s->d_out);
-    DVQ_REQUIRE(batch >= 1 && batch <= 65536, "batch=%d outside 1..65536", batch);
-    return DVQ_OK;
 }
 
 static GemmArgs ga(int M, int N, int K, const float* A, int64_t sam, int64_t sak, const float* B,

@@ -1,0 +1,469 @@
+// Fused warm-start MLP: one training step (input standardisation, forward,
+// loss, backward, AdamW) in two launches, and a one-launch forward pass.
+//
+// Same arithmetic as the GEMM-per-layer path of mlp.hip: every GEMM operand
+// rounded to bfloat16, float32 accumulation on the matrix cores
+// (v_mfma_f32_16x16x32_bf16), bias, ReLU, ReLU masks and the bias gradients
+// in float32 on the unrounded values.
+//
+// Layout.  A workgroup (4 wavefronts) owns a chunk of 32 batch rows and
+// keeps that chunk's activations in LDS as bfloat16, row-major where they
+// are the A operand of a product and transposed where the batch index is
+// the contraction index (the weight-gradient products), so every operand
+// fragment is one 16-byte LDS read.  Weights are read from the float32
+// master copy (L2-resident, 77 K parameters) and rounded as they are
+// loaded.  Everything a chunk contributes to the gradient is a sum over its
+// own rows, so the backward pass needs no other chunk: each workgroup writes
+// its partial gradient; the second launch sums the partials in chunk order
+// (bit-reproducible) and applies AdamW.
+#include "mlp_common.h"
+
+namespace dvq {
+
+constexpr int kFR = 32;          // batch rows per workgroup
+constexpr int kFRS = kFR + 8;    // row stride (elements) of the transposed [*][rows] arrays
+constexpr int kFKin = 32;        // first-layer contraction (d_in padded)
+constexpr int kFDmax = 128;      // largest d_out of the fused kernels
+constexpr int kFDS = kFDmax + 8; // row stride of dY
+constexpr int kFThreads = 256;
+
+template <int H>
+struct FusedLds {
+    static constexpr int HS = H + 8;  // row stride of the [rows][H] arrays
+    __bf16 xs[kFR * (kFKin + 8)];     // standardised X, [r][k]
+    __bf16 xT[kFKin * kFRS];          // the same, [k][r]
+    __bf16 h1[kFR * HS];              // relu(layer 1), [r][h]
+    __bf16 h1T[H * kFRS];             // [h][r]
+    __bf16 h2[kFR * HS];              // relu(layer 2), [r][h]; dZ2 after the mask
+    __bf16 h2T[H * kFRS];             // [h][r]; dZ1^T after dW3
+    __bf16 dy[kFR * kFDS];            // dY, [r][d]
+    __bf16 dyT[kFDmax * kFRS];        // [d][r]
+    __bf16 dz2T[H * kFRS];            // [h][r]
+    float colsum[2][H > kFDmax ? H : kFDmax];
+    double loss[kFThreads / 64];
+};
+
+// MFMA 16x16x32 fragments: lane l holds row (or column) l & 15 and the
+// contraction indices 8 (l >> 4) .. 8 (l >> 4) + 7.
+__device__ __forceinline__ bf16x8 frag_lds(const __bf16* base, int ld, int row0, int k0, int lane) {
+    return *reinterpret_cast<const bf16x8*>(base + (row0 + (lane & 15)) * ld + k0 + 8 * (lane >> 4));
+}
+
+// B[k][n] = W[n][k] from a row-major float32 W[nmax][ldw] (contiguous in k).
+__device__ __forceinline__ bf16x8 frag_w(const float* __restrict__ W, int ldw, int nmax, int kmax, int n0, int k0,
+                                         int lane) {
+    const int n = n0 + (lane & 15), kb = k0 + 8 * (lane >> 4);
+    bf16x8 v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = (n < nmax && kb + j < kmax) ? to_bf16(W[(int64_t)n * ldw + kb + j]) : to_bf16(0.f);
+    return v;
+}
+
+// B[k][n] = W[k][n] from a row-major float32 W[kmax][ldw] (strided in k).
+__device__ __forceinline__ bf16x8 frag_wt(const float* __restrict__ W, int ldw, int nmax, int kmax, int n0, int k0,
+                                          int lane) {
+    const int n = n0 + (lane & 15), kb = k0 + 8 * (lane >> 4);
+    bf16x8 v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = (n < nmax && kb + j < kmax) ? to_bf16(W[(int64_t)(kb + j) * ldw + n]) : to_bf16(0.f);
+    return v;
+}
+
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Sum over the 16 rows of an output tile of one column (lanes l, l + 16,
+// l + 32, l + 48 hold rows 4q .. 4q + 3 of column l & 15); lanes 0..15 get it.
+__device__ __forceinline__ float tile_colsum(f32x4 v) {
+    float s = (v[0] + v[1]) + (v[2] + v[3]);
+    s += __shfl_xor(s, 16, 64);
+    s += __shfl_xor(s, 32, 64);
+    return s;
+}
+
+// Forward pass of one chunk: xs/xT, h1/h1T, h2/h2T in LDS; returns nothing,
+// leaves the layer-3 tiles to the caller (epilogue differs between training
+// and inference).
+template <int H>
+__device__ __forceinline__ void fused_forward_hidden(FusedLds<H>& S, const float* __restrict__ params,
+                                                     const MlpOffsets& o, int d_in, const float* __restrict__ X,
+                                                     int x_rows, const int32_t* __restrict__ rows, int row0,
+                                                     int nrows, const float* __restrict__ mu,
+                                                     const float* __restrict__ isd) {
+    constexpr int HS = FusedLds<H>::HS;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // standardised inputs (zeros past the batch and past d_in)
+    for (int e = tid; e < kFR * kFKin; e += kFThreads) {
+        const int r = e / kFKin, k = e - r * kFKin;
+        float v = 0.f;
+        if (r < nrows && k < d_in) {
+            const int64_t src = rows ? (int64_t)rows[row0 + r] : (int64_t)(row0 + r);
+            if (src >= 0 && src < x_rows) {
+                v = X[src * d_in + k];
+                if (mu) v = (v - mu[k]) * isd[k];
+            }
+        }
+        const __bf16 q = to_bf16(v);
+        S.xs[r * (kFKin + 8) + k] = q;
+        S.xT[k * kFRS + r] = q;
+    }
+    __syncthreads();
+    // layer 1: [32 x 32] x W1^T, one contraction step per tile
+    for (int t = wave; t < 2 * (H / 16); t += 4) {
+        const int tm = t & 1, tn = t >> 1;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mfma(frag_lds(S.xs, kFKin + 8, 16 * tm, 0, lane), frag_w(params + o.W1, d_in, H, d_in, 16 * tn, 0, lane),
+                   acc);
+        const int n = 16 * tn + (lane & 15);
+        const float bias = params[o.b1 + n];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * tm + 4 * (lane >> 4) + i;
+            const __bf16 q = to_bf16(fmaxf(acc[i] + bias, 0.f));
+            S.h1[r * HS + n] = q;
+            S.h1T[n * kFRS + r] = q;
+        }
+    }
+    __syncthreads();
+    // layer 2: [32 x H] x W2^T
+    for (int t = wave; t < 2 * (H / 16); t += 4) {
+        const int tm = t & 1, tn = t >> 1;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < H; k0 += 32)
+            acc = mfma(frag_lds(S.h1, HS, 16 * tm, k0, lane), frag_w(params + o.W2, H, H, H, 16 * tn, k0, lane), acc);
+        const int n = 16 * tn + (lane & 15);
+        const float bias = params[o.b2 + n];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * tm + 4 * (lane >> 4) + i;
+            const __bf16 q = to_bf16(fmaxf(acc[i] + bias, 0.f));
+            S.h2[r * HS + n] = q;
+            S.h2T[n * kFRS + r] = q;
+        }
+    }
+    __syncthreads();
+}
+
+// Layer 3 of tile t: returns the float32 outputs (bias added).
+template <int H>
+__device__ __forceinline__ f32x4 fused_layer3(const FusedLds<H>& S, const float* __restrict__ params,
+                                              const MlpOffsets& o, int d_out, int tm, int tn, int lane) {
+    constexpr int HS = FusedLds<H>::HS;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < H; k0 += 32)
+        acc = mfma(frag_lds(S.h2, HS, 16 * tm, k0, lane), frag_w(params + o.W3, H, d_out, H, 16 * tn, k0, lane), acc);
+    const int n = 16 * tn + (lane & 15);
+    const float bias = n < d_out ? params[o.b3 + n] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] += bias;
+    return acc;
+}
+
+template <int H>
+__global__ void __launch_bounds__(kFThreads)
+k_mlp_predict(const float* __restrict__ params, int d_in, int d_out, const float* __restrict__ X, int batch,
+              const float* __restrict__ mu, const float* __restrict__ isd, float* __restrict__ Y) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    FusedLds<H>& S = *reinterpret_cast<FusedLds<H>*>(smem);
+    const dvq_mlp_shape sh{d_in, H, d_out};
+    const MlpOffsets o = offsets(sh);
+    const int row0 = blockIdx.x * kFR, nrows = batch - row0 < kFR ? batch - row0 : kFR;
+    fused_forward_hidden<H>(S, params, o, d_in, X, batch, nullptr, row0, nrows, mu, isd);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ntn = (d_out + 15) / 16;
+    for (int t = wave; t < 2 * ntn; t += 4) {
+        const int tm = t & 1, tn = t >> 1;
+        const f32x4 y = fused_layer3<H>(S, params, o, d_out, tm, tn, lane);
+        const int n = 16 * tn + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * tm + 4 * (lane >> 4) + i;
+            if (r < nrows && n < d_out) Y[(int64_t)(row0 + r) * d_out + n] = y[i];
+        }
+    }
+}
+
+// One chunk's forward pass, loss and partial gradient (same packing as the
+// parameters) into pg[blockIdx.x][*]; its loss sum into lossp[blockIdx.x].
+template <int H>
+__global__ void __launch_bounds__(kFThreads)
+k_mlp_train_chunk(const float* __restrict__ params, int d_in, int d_out, const float* __restrict__ X,
+                  const float* __restrict__ T, int x_rows, const int32_t* __restrict__ rows, int batch,
+                  const float* __restrict__ mu, const float* __restrict__ isd, float* __restrict__ pg,
+                  double* __restrict__ lossp) {
+    constexpr int HS = FusedLds<H>::HS;
+    extern __shared__ __align__(16) unsigned char smem[];
+    FusedLds<H>& S = *reinterpret_cast<FusedLds<H>*>(smem);
+    const dvq_mlp_shape sh{d_in, H, d_out};
+    const MlpOffsets o = offsets(sh);
+    const int row0 = blockIdx.x * kFR, nrows = batch - row0 < kFR ? batch - row0 : kFR;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    float* g = pg + (int64_t)blockIdx.x * o.total;
+    fused_forward_hidden<H>(S, params, o, d_in, X, x_rows, rows, row0, nrows, mu, isd);
+
+    // layer 3, loss and dY = sin(Y - T) / (batch * d_out); zeros past the batch
+    const int ntn = (d_out + 15) / 16;
+    const float inv = 1.0f / ((float)batch * (float)d_out);
+    double lsum = 0.0;
+    for (int e = tid; e < kFR * kFDS; e += kFThreads) S.dy[e] = to_bf16(0.f);
+    for (int e = tid; e < kFDmax * kFRS; e += kFThreads) S.dyT[e] = to_bf16(0.f);
+    __syncthreads();
+    for (int t = wave; t < 2 * ntn; t += 4) {
+        const int tm = t & 1, tn = t >> 1;
+        const f32x4 y = fused_layer3<H>(S, params, o, d_out, tm, tn, lane);
+        const int n = 16 * tn + (lane & 15);
+        f32x4 d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * tm + 4 * (lane >> 4) + i;
+            const int64_t src = r < nrows ? (rows ? (int64_t)rows[row0 + r] : (int64_t)(row0 + r)) : -1;
+            if (src >= 0 && src < x_rows && n < d_out) {
+                const float diff = y[i] - T[src * d_out + n];
+                d[i] = sinf(diff) * inv;
+                lsum += 1.0 - cos((double)diff);
+            }
+            const __bf16 q = to_bf16(d[i]);
+            S.dy[r * kFDS + n] = q;
+            S.dyT[n * kFRS + r] = q;
+        }
+        const float cs = tile_colsum(d);
+        if (lane < 16) S.colsum[tm][n] = cs;
+    }
+    lsum = wave_sum(lsum);
+    if (lane == 0) S.loss[wave] = lsum;
+    __syncthreads();
+    if (tid == 0) lossp[blockIdx.x] = (S.loss[0] + S.loss[1]) + (S.loss[2] + S.loss[3]);
+    for (int n = tid; n < d_out; n += kFThreads) g[o.b3 + n] = S.colsum[0][n] + S.colsum[1][n];
+
+    // dW3 = dY^T h2 (contraction over the chunk's rows: one step)
+    for (int t = wave; t < ntn * (H / 16); t += 4) {
+        const int tm = t % ntn, tn = t / ntn;  // tm over d_out, tn over H
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mfma(frag_lds(S.dyT, kFRS, 16 * tm, 0, lane), frag_lds(S.h2T, kFRS, 16 * tn, 0, lane), acc);
+        const int n = 16 * tn + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int d = 16 * tm + 4 * (lane >> 4) + i;
+            if (d < d_out) g[o.W3 + (int64_t)d * H + n] = acc[i];
+        }
+    }
+    __syncthreads();  // the colsum buffer and h2T are reused below
+
+    // dZ2 = (dY W3) * [h2 > 0]; written over h2 (each element read and
+    // written by the lane that owns it) and as dz2T
+    const int kd = (d_out + 31) / 32 * 32;
+    for (int t = wave; t < 2 * (H / 16); t += 4) {
+        const int tm = t & 1, tn = t >> 1;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < kd; k0 += 32)
+            acc = mfma(frag_lds(S.dy, kFDS, 16 * tm, k0, lane), frag_wt(params + o.W3, H, H, d_out, 16 * tn, k0, lane),
+                       acc);
+        const int n = 16 * tn + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * tm + 4 * (lane >> 4) + i;
+            const bool on = (float)S.h2[r * HS + n] > 0.f;
+            acc[i] = on ? acc[i] : 0.f;
+            const __bf16 q = to_bf16(acc[i]);
+            S.h2[r * HS + n] = q;
+            S.dz2T[n * kFRS + r] = q;
+        }
+        const float cs = tile_colsum(acc);
+        if (lane < 16) S.colsum[tm][n] = cs;
+    }
+    __syncthreads();
+    for (int n = tid; n < H; n += kFThreads) g[o.b2 + n] = S.colsum[0][n] + S.colsum[1][n];
+
+    // dW2 = dZ2^T h1
+    for (int t = wave; t < (H / 16) * (H / 16); t += 4) {
+        const int tm = t % (H / 16), tn = t / (H / 16);
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mfma(frag_lds(S.dz2T, kFRS, 16 * tm, 0, lane), frag_lds(S.h1T, kFRS, 16 * tn, 0, lane), acc);
+        const int n = 16 * tn + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) g[o.W2 + (int64_t)(16 * tm + 4 * (lane >> 4) + i) * H + n] = acc[i];
+    }
+    __syncthreads();  // the colsum buffer is reused below
+
+    // dZ1 = (dZ2 W2) * [h1 > 0], as dZ1^T over h2T
+    for (int t = wave; t < 2 * (H / 16); t += 4) {
+        const int tm = t & 1, tn = t >> 1;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < H; k0 += 32)
+            acc = mfma(frag_lds(S.h2, HS, 16 * tm, k0, lane), frag_wt(params + o.W2, H, H, H, 16 * tn, k0, lane), acc);
+        const int n = 16 * tn + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * tm + 4 * (lane >> 4) + i;
+            const bool on = (float)S.h1[r * HS + n] > 0.f;
+            acc[i] = on ? acc[i] : 0.f;
+            S.h2T[n * kFRS + r] = to_bf16(acc[i]);
+        }
+        const float cs = tile_colsum(acc);
+        if (lane < 16) S.colsum[tm][n] = cs;
+    }
+    __syncthreads();
+    for (int n = tid; n < H; n += kFThreads) g[o.b1 + n] = S.colsum[0][n] + S.colsum[1][n];
+
+    // dW1 = dZ1^T X
+    const int nti = (d_in + 15) / 16;
+    for (int t = wave; t < (H / 16) * nti; t += 4) {
+        const int tm = t % (H / 16), tn = t / (H / 16);
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mfma(frag_lds(S.h2T, kFRS, 16 * tm, 0, lane), frag_lds(S.xT, kFRS, 16 * tn, 0, lane), acc);
+        const int n = 16 * tn + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (n < d_in) g[o.W1 + (int64_t)(16 * tm + 4 * (lane >> 4) + i) * d_in + n] = acc[i];
+    }
+}
+
+// Sum of the chunks' partial gradients (chunk order), then AdamW; the loss
+// sum over chunks into loss[0] (mean over batch x d_out).
+__global__ void __launch_bounds__(256)
+k_mlp_reduce_adamw(const float* __restrict__ pg, int chunks, int64_t count, float* __restrict__ p,
+                   float* __restrict__ m, float* __restrict__ v, float lr, float b1, float b2, float eps, float wd,
+                   float c1, float c2, float* __restrict__ grads, const double* __restrict__ lossp, double inv_count,
+                   double* __restrict__ loss) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+        float gi = 0.f;
+        for (int c = 0; c < chunks; ++c) gi += pg[(int64_t)c * count + i];
+        if (grads) grads[i] = gi;
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * ((mi / c1) / (sqrtf(vi / c2) + eps) + wd * p[i]);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && loss) {
+        double s = 0.0;
+        for (int c = 0; c < chunks; ++c) s += lossp[c];
+        *loss = s * inv_count;
+    }
+}
+
+// Column mean and 1 / standard deviation (n - 1 denominator, at least
+// 1e-12) of X [rows][d], float64 sums in row order.
+__global__ void __launch_bounds__(64) k_feature_stats(const float* __restrict__ X, int rows, int d,
+                                                     float* __restrict__ mean, float* __restrict__ inv_std) {
+    const int k = blockIdx.x;
+    double s = 0.0;
+    for (int r = threadIdx.x; r < rows; r += 64) s += X[(int64_t)r * d + k];
+    s = wave_sum(s);
+    const double mu = s / rows;
+    double q = 0.0;
+    for (int r = threadIdx.x; r < rows; r += 64) {
+        const double e = X[(int64_t)r * d + k] - mu;
+        q += e * e;
+    }
+    q = wave_sum(q);
+    if (threadIdx.x == 0) {
+        const double sd = rows > 1 ? sqrt(q / (rows - 1)) : 0.0;
+        mean[k] = (float)mu;
+        inv_std[k] = (float)(1.0 / (sd > 1e-12 ? sd : 1e-12));
+    }
+}
+
+static bool fused_shape(const dvq_mlp_shape& s) {
+    return s.d_in <= kFKin && s.d_out <= kFDmax && (s.hidden == 64 || s.hidden == 128 || s.hidden == 256);
+}
+
+template <int H>
+static dvq_status launch_train_chunks(const dvq_mlp_shape& s, const float* params, const float* X, const float* T,
+                                      int x_rows, const int32_t* rows, int batch, const float* mu, const float* isd, float* pg,
+                                      double* lossp, hipStream_t hs) {
+    const size_t lds = sizeof(FusedLds<H>);
+    DVQ_TRY_HIP(allow_lds((const void*)k_mlp_train_chunk<H>, lds));
+    hipLaunchKernelGGL(k_mlp_train_chunk<H>, dim3((batch + kFR - 1) / kFR), dim3(kFThreads), lds, hs, params, s.d_in,
+                       s.d_out, X, T, x_rows, rows, batch, mu, isd, pg, lossp);
+    DVQ_CHECK_LAUNCH("k_mlp_train_chunk");
+    return DVQ_OK;
+}
+
+template <int H>
+static dvq_status launch_predict(const dvq_mlp_shape& s, const float* params, const float* X, int batch,
+                                 const float* mu, const float* isd, float* Y, hipStream_t hs) {
+    const size_t lds = sizeof(FusedLds<H>);
+    DVQ_TRY_HIP(allow_lds((const void*)k_mlp_predict<H>, lds));
+    hipLaunchKernelGGL(k_mlp_predict<H>, dim3((batch + kFR - 1) / kFR), dim3(kFThreads), lds, hs, params, s.d_in,
+                       s.d_out, X, batch, mu, isd, Y);
+    DVQ_CHECK_LAUNCH("k_mlp_predict");
+    return DVQ_OK;
+}
+
+}  // namespace dvq
+
+using namespace dvq;
+
+extern "C" {
+
+size_t dvq_mlp_train_workspace_bytes(const dvq_mlp_shape* s, int32_t batch) {
+    if (!s || batch < 1) return 0;
+    const int64_t chunks = (batch + kFR - 1) / kFR;
+    return (size_t)chunks * (size_t)offsets(*s).total * sizeof(float) + (size_t)chunks * sizeof(double);
+}
+
+dvq_status dvq_mlp_train_step(const dvq_mlp_shape* shape, float* params, float* m, float* v, int32_t t, float lr,
+                              float beta1, float beta2, float eps, float weight_decay, const float* X,
+                              const float* T, int32_t x_rows, const int32_t* rows, int32_t batch, const float* feat_mean,
+                              const float* feat_inv_std, float* grads, double* loss, void* workspace,
+                              size_t workspace_bytes, dvq_stream stream) {
+    dvq_status st = check_shape(shape, batch);
+    if (st != DVQ_OK) return st;
+    DVQ_REQUIRE(params && m && v && X && T, "null device pointer");
+    DVQ_REQUIRE((feat_mean == nullptr) == (feat_inv_std == nullptr), "feat_mean and feat_inv_std go together");
+    DVQ_REQUIRE(t >= 1, "t=%d < 1", t);
+    DVQ_REQUIRE(x_rows >= 1 && (rows != nullptr || batch <= x_rows), "x_rows=%d, batch=%d", x_rows, batch);
+    if (!fused_shape(*shape))
+        return fail(DVQ_EUNSUPPORTED, "fused MLP needs d_in <= %d, d_out <= %d, hidden 64/128/256", kFKin, kFDmax);
+    const size_t need = dvq_mlp_train_workspace_bytes(shape, batch);
+    if (!workspace || workspace_bytes < need)
+        return fail(DVQ_ECAPACITY, "mlp train workspace %zu B < %zu B", workspace_bytes, need);
+    const dvq_mlp_shape s = *shape;
+    const int64_t count = offsets(s).total;
+    const int chunks = (batch + kFR - 1) / kFR;
+    float* pg = static_cast<float*>(workspace);
+    double* lossp = reinterpret_cast<double*>(static_cast<char*>(workspace) + (size_t)chunks * count * sizeof(float));
+    hipStream_t hs = stream_of(stream);
+    if (s.hidden == 64)
+        st = launch_train_chunks<64>(s, params, X, T, x_rows, rows, batch, feat_mean, feat_inv_std, pg, lossp, hs);
+    else if (s.hidden == 128)
+        st = launch_train_chunks<128>(s, params, X, T, x_rows, rows, batch, feat_mean, feat_inv_std, pg, lossp, hs);
+    else
+        st = launch_train_chunks<256>(s, params, X, T, x_rows, rows, batch, feat_mean, feat_inv_std, pg, lossp, hs);
+    if (st != DVQ_OK) return st;
+    const float c1 = 1.f - powf(beta1, (float)t), c2 = 1.f - powf(beta2, (float)t);
+    const int64_t blocks = (count + 255) / 256 < 1024 ? (count + 255) / 256 : 1024;
+    hipLaunchKernelGGL(k_mlp_reduce_adamw, dim3((unsigned)blocks), dim3(256), 0, hs, pg, chunks, count, params, m, v,
+                       lr, beta1, beta2, eps, weight_decay, c1, c2, grads, lossp, 1.0 / ((double)batch * s.d_out),
+                       loss);
+    DVQ_CHECK_LAUNCH("k_mlp_reduce_adamw");
+    return DVQ_OK;
+}
+
+dvq_status dvq_mlp_predict(const dvq_mlp_shape* shape, const float* params, const float* X, int32_t batch,
+                           const float* feat_mean, const float* feat_inv_std, float* Y, dvq_stream stream) {
+    dvq_status st = check_shape(shape, batch);
+    if (st != DVQ_OK) return st;
+    DVQ_REQUIRE(params && X && Y, "null device pointer");
+    DVQ_REQUIRE((feat_mean == nullptr) == (feat_inv_std == nullptr), "feat_mean and feat_inv_std go together");
+    if (!fused_shape(*shape))
+        return fail(DVQ_EUNSUPPORTED, "fused MLP needs d_in <= %d, d_out <= %d, hidden 64/128/256", kFKin, kFDmax);
+    const dvq_mlp_shape s = *shape;
+    hipStream_t hs = stream_of(stream);
+    if (s.hidden == 64) return launch_predict<64>(s, params, X, batch, feat_mean, feat_inv_std, Y, hs);
+    if (s.hidden == 128) return launch_predict<128>(s, params, X, batch, feat_mean, feat_inv_std, Y, hs);
+    return launch_predict<256>(s, params, X, batch, feat_mean, feat_inv_std, Y, hs);
+}
+
+dvq_status dvq_feature_stats(const float* X, int32_t rows, int32_t d, float* mean, float* inv_std,
+                             dvq_stream stream) {
+    DVQ_REQUIRE(X && mean && inv_std, "null device pointer");
+    DVQ_REQUIRE(rows >= 1 && d >= 1 && d <= 65536, "rows=%d, d=%d out of range", rows, d);
+    hipLaunchKernelGGL(k_feature_stats, dim3(d), dim3(64), 0, stream_of(stream), X, rows, d, mean, inv_std);
+    DVQ_CHECK_LAUNCH("k_feature_stats");
+    return DVQ_OK;
+}
+
+}  // extern "C"

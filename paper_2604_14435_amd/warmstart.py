@@ -8,7 +8,8 @@ calls and moves tensors):
      every system started from one common angle vector (the solution of a
      reference system), so the optimised angles vary smoothly over the family;
   3. train the bfloat16 MLP (descriptor -> angles) with the wrap-safe loss
-     mean(1 - cos(pred - target)) and AdamW;
+     mean(1 - cos(pred - target)) and AdamW, one fused kernel pair per
+     minibatch (inputs standardised on the device);
   4. predict initial angles for new systems; random initialisation remains
      the reference and the fallback (a prediction whose cost is not finite or
      is worse than the random start's is replaced by the random start).
@@ -118,19 +119,25 @@ class MLPConfig:
 
 
 class WarmStartMLP:
-    """d_in -> hidden -> hidden -> P network on the bfloat16 matrix cores."""
+    """d_in -> hidden -> hidden -> P network on the bfloat16 matrix cores.
+
+    Training and inference run the fused kernels (dvq_mlp_train_step: one
+    minibatch step in two launches; dvq_mlp_predict): the input
+    standardisation statistics are computed by the library
+    (dvq_feature_stats) and applied inside the kernels; Python only draws
+    the epoch's row permutation (host generator) and orders the calls."""
 
     def __init__(self, d_in: int, d_out: int, cfg: MLPConfig = MLPConfig(), device="cuda:0"):
+        if d_in > 32 or d_out > 128 or cfg.hidden not in (64, 128, 256):
+            raise ValueError("the fused MLP kernels take d_in <= 32, d_out <= 128, hidden 64/128/256")
         self.cfg = cfg
         self.device = torch.device(device)
         self.shape = api.mlp_shape(d_in, cfg.hidden, d_out)
         self.params = self.init_params(d_in, cfg.hidden, d_out, cfg.seed).to(self.device)
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
-        self.grads = torch.empty_like(self.params)
         self.t = 0
-        self.mu = torch.zeros(d_in, dtype=torch.float32, device=self.device)
-        self.sd = torch.ones(d_in, dtype=torch.float32, device=self.device)
+        self.stats = None  # (mean, 1/std) of the training inputs, device float32
 
     @staticmethod
     def init_params(d_in: int, hidden: int, d_out: int, seed: int) -> torch.Tensor:
@@ -146,51 +153,36 @@ class WarmStartMLP:
                                w(d_out, hidden), z(d_out)])
         return torch.from_numpy(flat)
 
-    def _features(self, X) -> torch.Tensor:
-        X = torch.as_tensor(X, dtype=torch.float32, device=self.device)
-        return ((X - self.mu) / self.sd).contiguous()
-
     def fit(self, X, T, epochs: int | None = None):
         """Train on descriptors X [S, d_in] and angles T [S, P]; returns the
         per-epoch mean loss (float64 numpy)."""
         cfg = self.cfg
-        X = torch.as_tensor(X, dtype=torch.float32, device=self.device)
-        self.mu = X.mean(0)
-        self.sd = X.std(0).clamp_min(1e-12)
-        Xf = self._features(X)
+        X = torch.as_tensor(X, dtype=torch.float32, device=self.device).contiguous()
         T = torch.as_tensor(T, dtype=torch.float32, device=self.device).contiguous()
-        S = Xf.shape[0]
+        self.stats = api.feature_stats(X)
+        S = X.shape[0]
         bs = min(cfg.batch, S)
+        steps = S // bs
+        n_ep = epochs if epochs is not None else cfg.epochs
         gen = torch.Generator().manual_seed(cfg.seed)
-        ws = None
-        losses = []
-        for _ in range(epochs if epochs is not None else cfg.epochs):
-            perm = torch.randperm(S, generator=gen).to(self.device)
-            tot = torch.zeros(1, dtype=torch.float64, device=self.device)
-            nb = 0
-            for s0 in range(0, S - bs + 1, bs):
-                idx = perm[s0:s0 + bs]
-                xb, tb = Xf[idx].contiguous(), T[idx].contiguous()
-                Y, H1, H2 = api.mlp_forward(self.shape, self.params, xb)
-                dY, loss = api.mlp_loss_grad(Y, tb)
-                if ws is None:
-                    import ctypes
-                    from . import _lib
-                    ws = torch.empty(_lib.load().dvq_mlp_workspace_bytes(ctypes.byref(self.shape), bs),
-                                     dtype=torch.uint8, device=self.device)
-                api.mlp_backward(self.shape, self.params, xb, H1, H2, dY, ws, out=self.grads)
+        ws = api.TrainWorkspace(self.shape, bs, self.device)
+        losses = torch.empty(n_ep * steps, dtype=torch.float64, device=self.device)
+        # every epoch's row permutation, drawn on the host and uploaded once
+        perms = torch.stack([torch.randperm(S, generator=gen) for _ in range(n_ep)]).to(torch.int32)
+        perms = perms.to(self.device)
+        for e in range(n_ep):
+            for j in range(steps):
                 self.t += 1
-                api.adamw_step(self.params, self.grads, self.m, self.v, self.t, cfg.lr,
-                               weight_decay=cfg.weight_decay)
-                tot += loss
-                nb += 1
-            losses.append(tot / max(nb, 1))
-        return torch.cat(losses).cpu().numpy()
+                k = e * steps + j
+                api.mlp_train_step(self.shape, self.params, self.m, self.v, self.t, X, T,
+                                   rows=perms[e, j * bs:(j + 1) * bs], stats=self.stats, lr=cfg.lr,
+                                   weight_decay=cfg.weight_decay, workspace=ws, loss=losses[k:k + 1])
+        return losses.cpu().numpy().reshape(n_ep, steps).mean(axis=1)
 
     def predict(self, X) -> torch.Tensor:
         """Initial angles [S, P] as float64."""
-        Y, _, _ = api.mlp_forward(self.shape, self.params, self._features(X))
-        return Y.double()
+        X = torch.as_tensor(X, dtype=torch.float32, device=self.device).contiguous()
+        return api.mlp_predict(self.shape, self.params, X, stats=self.stats).double()
 
 
 def choose_start(ansatz, coeffs, strings, theta_pred, theta_rand, kind="local", precision="f32"):
@@ -201,3 +193,43 @@ def choose_start(ansatz, coeffs, strings, theta_pred, theta_rand, kind="local", 
     Cr, _ = api.vqls_grad_adjoint(ansatz, theta_rand, coeffs, strings, kind, precision, per_row_system=True)
     use = torch.isfinite(Cp) & (Cp <= Cr)
     return torch.where(use.unsqueeze(1), theta_pred, theta_rand), use
+
+
+def continuation_targets(ansatz: api.AnsatzSpec, ab: np.ndarray, coeffs: torch.Tensor, strings: torch.Tensor,
+                         theta_centre: np.ndarray, centre, bins: int = 16, iters: int = 100,
+                         precision: str = "f64", kind: str = "local") -> tuple[np.ndarray, np.ndarray]:
+    """Training angles for a family by continuation in the off-diagonal b:
+    the family is cut into `bins` bins of b; the bin holding the centre
+    system starts from its solution, and every further bin, taken outward
+    from there, starts each system from the solution of the nearest
+    already-solved system in (a, b).  Each bin is solved by one batched
+    L-BFGS run (complex128 adjoint).  Neighbouring systems thus start close
+    to each other's solutions and stay on one branch of the solution set,
+    which is what a network can interpolate.  Returns (theta [S, P],
+    final cost [S])."""
+    from .optim import BatchEvaluator, lbfgs_batched
+
+    S = len(ab)
+    edges = np.linspace(ab[:, 1].min(), ab[:, 1].max() + 1e-12, bins + 1)
+    which = np.clip(np.searchsorted(edges, ab[:, 1], side="right") - 1, 0, bins - 1)
+    c_bin = int(np.clip(np.searchsorted(edges, centre[1], side="right") - 1, 0, bins - 1))
+    order = [c_bin] + [b for d in range(1, bins) for b in (c_bin - d, c_bin + d) if 0 <= b < bins]
+    theta = np.zeros((S, ansatz.P))
+    cost = np.full(S, np.inf)
+    solved = np.zeros(S, dtype=bool)
+    for b in order:
+        idx = np.nonzero(which == b)[0]
+        if len(idx) == 0:
+            continue
+        if not solved.any():
+            start = np.tile(theta_centre, (len(idx), 1))
+        else:
+            done = np.nonzero(solved)[0]
+            d2 = ((ab[idx, None, :] - ab[None, done, :]) ** 2).sum(-1)
+            start = theta[done[np.argmin(d2, axis=1)]]
+        sel = torch.from_numpy(idx).to(coeffs.device)
+        ev = BatchEvaluator(ansatz, coeffs[sel].contiguous(), strings[sel].contiguous(), precision, kind)
+        th, f = lbfgs_batched(ev, start, iters=iters)
+        theta[idx], cost[idx] = th, f
+        solved[idx] = True
+    return theta, cost

@@ -145,3 +145,106 @@ def test_warm_start_beats_random_init():
     it_r = np.where(it_r < 0, budget + 1, it_r)
     it_w = np.where(it_w < 0, budget + 1, it_w)
     assert np.median(it_w) < 0.5 * np.median(it_r), (np.median(it_w), np.median(it_r))
+
+
+# ------------------------------------------------------------ fused kernels
+
+def _std(X):
+    mu = X.mean(0).astype(np.float32)
+    sd = X.std(0, ddof=1)
+    isd = (1.0 / np.maximum(sd, 1e-12)).astype(np.float32)
+    return mu, isd
+
+
+def test_feature_stats_match_numpy():
+    rng = np.random.default_rng(7)
+    X = (rng.standard_normal((1000, 3)) * [1.0, 5.0, 0.01] + [3.0, -2.0, 0.5]).astype(np.float32)
+    mean, isd = api.feature_stats(torch.from_numpy(X).to(DEV))
+    mu, want = _std(X.astype(np.float64))
+    assert np.allclose(mean.cpu().numpy(), mu, rtol=1e-6, atol=1e-6)
+    assert np.allclose(isd.cpu().numpy(), want, rtol=1e-6)
+
+
+@pytest.mark.parametrize("d_in,h,d_out,B", [(2, 256, 40, 256), (2, 256, 80, 100), (2, 64, 40, 37), (5, 128, 18, 3)])
+def test_fused_predict_matches_oracle(d_in, h, d_out, B):
+    """One-launch forward with on-device standardisation against the FP64
+    oracle fed the same standardised float32 inputs."""
+    rng = np.random.default_rng(d_in + h + d_out)
+    p = om.init_params(d_in, h, d_out, seed=4)
+    for k in ("b1", "b2", "b3"):
+        p[k] = (0.1 * rng.standard_normal(p[k].shape)).astype(np.float32).astype(np.float64)
+    X = (rng.standard_normal((B, d_in)) * 0.3 + 1.0).astype(np.float32)
+    mu, isd = _std(X.astype(np.float64))
+    shape = api.mlp_shape(d_in, h, d_out)
+    params = torch.from_numpy(_pack(p)).to(DEV)
+    Y = api.mlp_predict(shape, params, torch.from_numpy(X).to(DEV),
+                        stats=(torch.from_numpy(mu).to(DEV), torch.from_numpy(isd).to(DEV)))
+    Xs = ((X - mu) * isd).astype(np.float32)
+    y, _ = om.forward(p, Xs.astype(np.float64))
+    _close(Y.cpu().numpy(), y)
+
+
+@pytest.mark.parametrize("d_in,h,d_out,B", [(2, 256, 40, 256), (2, 256, 80, 70), (3, 64, 12, 37)])
+def test_fused_train_step_matches_oracle(d_in, h, d_out, B):
+    """One fused step on a minibatch chosen by a row-index array: loss,
+    gradient (packed) and the AdamW update against the oracle's forward,
+    loss, backward and AdamW on the same rows."""
+    rng = np.random.default_rng(11 + h)
+    S = B + 50
+    p = om.init_params(d_in, h, d_out, seed=5)
+    for k in ("b1", "b2", "b3"):
+        p[k] = (0.1 * rng.standard_normal(p[k].shape)).astype(np.float32).astype(np.float64)
+    X = (rng.standard_normal((S, d_in)) * 0.5 + 0.2).astype(np.float32)
+    T = rng.uniform(-math.pi, math.pi, (S, d_out)).astype(np.float32)
+    rows = rng.permutation(S)[:B].astype(np.int32)
+    mu, isd = _std(X[rows].astype(np.float64))
+    shape = api.mlp_shape(d_in, h, d_out)
+    flat = _pack(p)
+    params = torch.from_numpy(flat.copy()).to(DEV)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    loss = torch.empty(1, dtype=torch.float64, device=DEV)
+    grads = torch.empty_like(params)
+    api.mlp_train_step(shape, params, m, v, 1, torch.from_numpy(X).to(DEV), torch.from_numpy(T).to(DEV),
+                       rows=torch.from_numpy(rows).to(DEV),
+                       stats=(torch.from_numpy(mu).to(DEV), torch.from_numpy(isd).to(DEV)),
+                       lr=1e-3, weight_decay=0.01, loss=loss, grads=grads)
+    Xs = ((X[rows] - mu) * isd).astype(np.float32).astype(np.float64)
+    y, cache = om.forward(p, Xs)
+    l_ref, dy = om.loss_and_grad_output(y, T[rows].astype(np.float64))
+    # the GPU rounds its own float32 dY; the oracle's float64 dY rounds the same way to bfloat16
+    gref = om.backward(p, cache, dy)
+    assert abs(loss.item() - l_ref) < 1e-5
+    gg = _unpack(grads.cpu().numpy(), d_in, h, d_out)
+    for k in om.LAYERS:
+        scale = max(1e-12, np.max(np.abs(gref[k])))
+        err = np.abs(gg[k] - gref[k]) / scale
+        assert np.median(err) < 1e-4 and np.max(err) < 1e-2, (k, np.median(err), np.max(err))
+    # the update is AdamW applied to the GPU's own gradient
+    pr = {k: x.copy() for k, x in p.items()}
+    mr = {k: np.zeros_like(x) for k, x in p.items()}
+    vr = {k: np.zeros_like(x) for k, x in p.items()}
+    om.adamw_step(pr, gg, mr, vr, 1, lr=1e-3, weight_decay=0.01)
+    got = _unpack(params.cpu().numpy(), d_in, h, d_out)
+    for k in om.LAYERS:
+        assert np.max(np.abs(got[k] - pr[k])) < 1e-6, k
+
+
+def test_fused_train_step_ignores_rows_outside_x():
+    """Row indices outside 0..rows(X)-1 contribute nothing: the same step
+    with those rows replaced by a different out-of-range value is bit-equal."""
+    rng = np.random.default_rng(3)
+    d_in, h, d_out, S = 2, 64, 8, 40
+    shape = api.mlp_shape(d_in, h, d_out)
+    X = torch.from_numpy(rng.standard_normal((S, d_in)).astype(np.float32)).to(DEV)
+    T = torch.from_numpy(rng.uniform(-1, 1, (S, d_out)).astype(np.float32)).to(DEV)
+    base = torch.from_numpy(_pack(om.init_params(d_in, h, d_out, seed=1))).to(DEV)
+    outs = []
+    for bad in (-5, S, 10 ** 6):
+        rows = torch.tensor([0, 3, bad, 7, 39, bad], dtype=torch.int32, device=DEV)
+        params, m, v = base.clone(), torch.zeros_like(base), torch.zeros_like(base)
+        g = torch.empty_like(base)
+        api.mlp_train_step(shape, params, m, v, 1, X, T, rows=rows, grads=g)
+        outs.append((params.clone(), g.clone()))
+    for p_, g_ in outs[1:]:
+        assert torch.equal(p_, outs[0][0]) and torch.equal(g_, outs[0][1])
