@@ -396,8 +396,8 @@ dvq_status dvq_feature_stats(const float* X, int32_t rows, int32_t d, float* mea
 dvq_status dvq_mlp_predict(const dvq_mlp_shape* shape, const float* params, const float* X, int32_t batch,
                            const float* feat_mean, const float* feat_inv_std, float* Y, dvq_stream stream);
 
-/* Scratch bytes for dvq_mlp_train_step: one partial gradient per chunk of
- * 32 rows plus one loss sum per chunk. */
+/* Scratch bytes for dvq_mlp_train_step: one partial gradient and one loss
+ * sum per chunk of 32 rows, and the bfloat16 copies of the weights. */
 size_t dvq_mlp_train_workspace_bytes(const dvq_mlp_shape* shape, int32_t batch);
 
 /*
@@ -410,8 +410,9 @@ size_t dvq_mlp_train_workspace_bytes(const dvq_mlp_shape* shape, int32_t batch);
  * (t >= 1 counts steps) on params, m, v in place.
  *   grads [param_count] receives the gradient (may be NULL).
  *   loss  [1] float64 receives the minibatch loss before the step (may be NULL).
- * Two launches: the chunks' forward and backward passes, then the
- * chunk-ordered sum of their gradients with the AdamW update.
+ * Three launches: the weights rounded to bfloat16 into the workspace (in
+ * the layouts the products read), the chunks' forward and backward passes,
+ * then the chunk-ordered sum of their gradients with the AdamW update.
  */
 dvq_status dvq_mlp_train_step(const dvq_mlp_shape* shape, float* params, float* m, float* v, int32_t t,
                               float lr, float beta1, float beta2, float eps, float weight_decay,

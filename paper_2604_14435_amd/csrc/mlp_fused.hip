@@ -1,21 +1,23 @@
 // Fused warm-start MLP: one training step (input standardisation, forward,
-// loss, backward, AdamW) in two launches, and a one-launch forward pass.
+// loss, backward, AdamW) in three launches, and a one-launch forward pass.
 //
 // Same arithmetic as the GEMM-per-layer path of mlp.hip: every GEMM operand
 // rounded to bfloat16, float32 accumulation on the matrix cores
 // (v_mfma_f32_16x16x32_bf16), bias, ReLU, ReLU masks and the bias gradients
 // in float32 on the unrounded values.
 //
-// Layout.  A workgroup (4 wavefronts) owns a chunk of 32 batch rows and
+// Layout.  A workgroup (16 wavefronts) owns a chunk of 32 batch rows and
 // keeps that chunk's activations in LDS as bfloat16, row-major where they
 // are the A operand of a product and transposed where the batch index is
 // the contraction index (the weight-gradient products), so every operand
-// fragment is one 16-byte LDS read.  Weights are read from the float32
-// master copy (L2-resident, 77 K parameters) and rounded as they are
-// loaded.  Everything a chunk contributes to the gradient is a sum over its
-// own rows, so the backward pass needs no other chunk: each workgroup writes
-// its partial gradient; the second launch sums the partials in chunk order
-// (bit-reproducible) and applies AdamW.
+// fragment is one 16-byte LDS read.  The forward pass reads the weights from
+// the float32 master copy (L2-resident, 77 K parameters) and rounds them as
+// they are loaded; the training step first makes a bfloat16 copy laid out so
+// that every weight fragment of the step is one 16-byte load (W2 and W3 also
+// transposed for the backward products).  Everything a chunk contributes to
+// the gradient is a sum over its own rows, so the backward pass needs no
+// other chunk: each workgroup writes its partial gradient; the last launch
+// sums the partials in chunk order (bit-reproducible) and applies AdamW.
 #include "mlp_common.h"
 
 namespace dvq {
@@ -25,7 +27,8 @@ constexpr int kFRS = kFR + 8;    // row stride (elements) of the transposed [*][
 constexpr int kFKin = 32;        // first-layer contraction (d_in padded)
 constexpr int kFDmax = 128;      // largest d_out of the fused kernels
 constexpr int kFDS = kFDmax + 8; // row stride of dY
-constexpr int kFThreads = 256;
+constexpr int kFWaves = 16;     // wavefronts per workgroup: the output tiles of a product spread over them
+constexpr int kFThreads = 64 * kFWaves;
 
 template <int H>
 struct FusedLds {
@@ -39,7 +42,8 @@ struct FusedLds {
     __bf16 dy[kFR * kFDS];            // dY, [r][d]
     __bf16 dyT[kFDmax * kFRS];        // [d][r]
     __bf16 dz2T[H * kFRS];            // [h][r]
-    float colsum[2][H > kFDmax ? H : kFDmax];
+    float colsum[2][H > kFDmax ? H : kFDmax];  // column sums for b3, then b1
+    float cs2[2][H];                           // column sums for b2
     double loss[kFThreads / 64];
 };
 
@@ -49,24 +53,79 @@ __device__ __forceinline__ bf16x8 frag_lds(const __bf16* base, int ld, int row0,
     return *reinterpret_cast<const bf16x8*>(base + (row0 + (lane & 15)) * ld + k0 + 8 * (lane >> 4));
 }
 
-// B[k][n] = W[n][k] from a row-major float32 W[nmax][ldw] (contiguous in k).
+// B[k][n] = W[n][k] from a row-major float32 W[nmax][ldw] (contiguous in k):
+// two 16-byte loads when the fragment is inside W and aligned.
 __device__ __forceinline__ bf16x8 frag_w(const float* __restrict__ W, int ldw, int nmax, int kmax, int n0, int k0,
                                          int lane) {
     const int n = n0 + (lane & 15), kb = k0 + 8 * (lane >> 4);
     bf16x8 v;
+    if (n < nmax && kb + 8 <= kmax && (ldw & 3) == 0) {
+        const float4* p = reinterpret_cast<const float4*>(W + (int64_t)n * ldw + kb);
+        const float4 a = p[0], b = p[1];
+        v[0] = to_bf16(a.x), v[1] = to_bf16(a.y), v[2] = to_bf16(a.z), v[3] = to_bf16(a.w);
+        v[4] = to_bf16(b.x), v[5] = to_bf16(b.y), v[6] = to_bf16(b.z), v[7] = to_bf16(b.w);
+        return v;
+    }
 #pragma unroll
     for (int j = 0; j < 8; ++j) v[j] = (n < nmax && kb + j < kmax) ? to_bf16(W[(int64_t)n * ldw + kb + j]) : to_bf16(0.f);
     return v;
 }
 
-// B[k][n] = W[k][n] from a row-major float32 W[kmax][ldw] (strided in k).
-__device__ __forceinline__ bf16x8 frag_wt(const float* __restrict__ W, int ldw, int nmax, int kmax, int n0, int k0,
-                                          int lane) {
-    const int n = n0 + (lane & 15), kb = k0 + 8 * (lane >> 4);
-    bf16x8 v;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = (n < nmax && kb + j < kmax) ? to_bf16(W[(int64_t)(kb + j) * ldw + n]) : to_bf16(0.f);
-    return v;
+// A fragment of a bfloat16 matrix in device memory (row stride ld elements,
+// multiple of 8): one 16-byte load per lane.
+__device__ __forceinline__ bf16x8 frag_g(const __bf16* __restrict__ W, int ld, int row0, int k0, int lane) {
+    return *reinterpret_cast<const bf16x8*>(W + (int64_t)(row0 + (lane & 15)) * ld + k0 + 8 * (lane >> 4));
+}
+
+// The weights of one training step, rounded to bfloat16 once and laid out so
+// that every B fragment of the step is contiguous (zero padding past d_in and
+// d_out): w1 [H][32] = W1; w2 [H][H] = W2; w2t [H][H] = W2^T; w3 [128][H] =
+// W3; w3t [H][128] = W3^T.
+struct W16 {
+    __bf16 *w1, *w2, *w2t, *w3, *w3t;
+};
+
+__host__ __device__ inline size_t w16_elems(int H) {
+    return (size_t)H * kFKin + 2 * (size_t)H * H + 2 * (size_t)kFDmax * H;
+}
+
+__host__ __device__ inline W16 w16_layout(void* base, int H) {
+    W16 w;
+    w.w1 = static_cast<__bf16*>(base);
+    w.w2 = w.w1 + (size_t)H * kFKin;
+    w.w2t = w.w2 + (size_t)H * H;
+    w.w3 = w.w2t + (size_t)H * H;
+    w.w3t = w.w3 + (size_t)kFDmax * H;
+    return w;
+}
+
+__global__ void __launch_bounds__(256)
+k_mlp_weights_bf16(const float* __restrict__ params, int H, int d_in, int d_out, W16 w) {
+    const dvq_mlp_shape sh{d_in, H, d_out};
+    const MlpOffsets o = offsets(sh);
+    const int64_t n1 = (int64_t)H * kFKin, n2 = (int64_t)H * H, n3 = (int64_t)kFDmax * H;
+    const int64_t total = n1 + 2 * n2 + 2 * n3;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        if (e < n1) {
+            const int h = (int)(e / kFKin), i = (int)(e % kFKin);
+            w.w1[e] = to_bf16(i < d_in ? params[o.W1 + (int64_t)h * d_in + i] : 0.f);
+        } else if (e < n1 + n2) {
+            const int64_t x = e - n1;
+            w.w2[x] = to_bf16(params[o.W2 + x]);
+        } else if (e < n1 + 2 * n2) {
+            const int64_t x = e - n1 - n2;
+            const int r = (int)(x / H), c = (int)(x % H);
+            w.w2t[x] = to_bf16(params[o.W2 + (int64_t)c * H + r]);
+        } else if (e < n1 + 2 * n2 + n3) {
+            const int64_t x = e - n1 - 2 * n2;
+            const int d = (int)(x / H), k = (int)(x % H);
+            w.w3[x] = to_bf16(d < d_out ? params[o.W3 + (int64_t)d * H + k] : 0.f);
+        } else {
+            const int64_t x = e - n1 - 2 * n2 - n3;
+            const int h = (int)(x / kFDmax), d = (int)(x % kFDmax);
+            w.w3t[x] = to_bf16(d < d_out ? params[o.W3 + (int64_t)d * H + h] : 0.f);
+        }
+    }
 }
 
 __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
@@ -85,9 +144,10 @@ __device__ __forceinline__ float tile_colsum(f32x4 v) {
 // Forward pass of one chunk: xs/xT, h1/h1T, h2/h2T in LDS; returns nothing,
 // leaves the layer-3 tiles to the caller (epilogue differs between training
 // and inference).
-template <int H>
+template <int H, bool PRE>
 __device__ __forceinline__ void fused_forward_hidden(FusedLds<H>& S, const float* __restrict__ params,
-                                                     const MlpOffsets& o, int d_in, const float* __restrict__ X,
+                                                     const W16& w, const MlpOffsets& o, int d_in,
+                                                     const float* __restrict__ X,
                                                      int x_rows, const int32_t* __restrict__ rows, int row0,
                                                      int nrows, const float* __restrict__ mu,
                                                      const float* __restrict__ isd) {
@@ -110,11 +170,11 @@ __device__ __forceinline__ void fused_forward_hidden(FusedLds<H>& S, const float
     }
     __syncthreads();
     // layer 1: [32 x 32] x W1^T, one contraction step per tile
-    for (int t = wave; t < 2 * (H / 16); t += 4) {
+    for (int t = wave; t < 2 * (H / 16); t += kFWaves) {
         const int tm = t & 1, tn = t >> 1;
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mfma(frag_lds(S.xs, kFKin + 8, 16 * tm, 0, lane), frag_w(params + o.W1, d_in, H, d_in, 16 * tn, 0, lane),
-                   acc);
+        const bf16x8 b = PRE ? frag_g(w.w1, kFKin, 16 * tn, 0, lane) : frag_w(params + o.W1, d_in, H, d_in, 16 * tn, 0, lane);
+        acc = mfma(frag_lds(S.xs, kFKin + 8, 16 * tm, 0, lane), b, acc);
         const int n = 16 * tn + (lane & 15);
         const float bias = params[o.b1 + n];
 #pragma unroll
@@ -127,11 +187,13 @@ __device__ __forceinline__ void fused_forward_hidden(FusedLds<H>& S, const float
     }
     __syncthreads();
     // layer 2: [32 x H] x W2^T
-    for (int t = wave; t < 2 * (H / 16); t += 4) {
+    for (int t = wave; t < 2 * (H / 16); t += kFWaves) {
         const int tm = t & 1, tn = t >> 1;
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
         for (int k0 = 0; k0 < H; k0 += 32)
-            acc = mfma(frag_lds(S.h1, HS, 16 * tm, k0, lane), frag_w(params + o.W2, H, H, H, 16 * tn, k0, lane), acc);
+            acc = mfma(frag_lds(S.h1, HS, 16 * tm, k0, lane),
+                       PRE ? frag_g(w.w2, H, 16 * tn, k0, lane) : frag_w(params + o.W2, H, H, H, 16 * tn, k0, lane), acc);
         const int n = 16 * tn + (lane & 15);
         const float bias = params[o.b2 + n];
 #pragma unroll
@@ -146,13 +208,15 @@ __device__ __forceinline__ void fused_forward_hidden(FusedLds<H>& S, const float
 }
 
 // Layer 3 of tile t: returns the float32 outputs (bias added).
-template <int H>
-__device__ __forceinline__ f32x4 fused_layer3(const FusedLds<H>& S, const float* __restrict__ params,
+template <int H, bool PRE>
+__device__ __forceinline__ f32x4 fused_layer3(const FusedLds<H>& S, const float* __restrict__ params, const W16& w,
                                               const MlpOffsets& o, int d_out, int tm, int tn, int lane) {
     constexpr int HS = FusedLds<H>::HS;
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
     for (int k0 = 0; k0 < H; k0 += 32)
-        acc = mfma(frag_lds(S.h2, HS, 16 * tm, k0, lane), frag_w(params + o.W3, H, d_out, H, 16 * tn, k0, lane), acc);
+        acc = mfma(frag_lds(S.h2, HS, 16 * tm, k0, lane),
+                   PRE ? frag_g(w.w3, H, 16 * tn, k0, lane) : frag_w(params + o.W3, H, d_out, H, 16 * tn, k0, lane), acc);
     const int n = 16 * tn + (lane & 15);
     const float bias = n < d_out ? params[o.b3 + n] : 0.f;
 #pragma unroll
@@ -169,12 +233,13 @@ k_mlp_predict(const float* __restrict__ params, int d_in, int d_out, const float
     const dvq_mlp_shape sh{d_in, H, d_out};
     const MlpOffsets o = offsets(sh);
     const int row0 = blockIdx.x * kFR, nrows = batch - row0 < kFR ? batch - row0 : kFR;
-    fused_forward_hidden<H>(S, params, o, d_in, X, batch, nullptr, row0, nrows, mu, isd);
+    const W16 w{};
+    fused_forward_hidden<H, false>(S, params, w, o, d_in, X, batch, nullptr, row0, nrows, mu, isd);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ntn = (d_out + 15) / 16;
-    for (int t = wave; t < 2 * ntn; t += 4) {
+    for (int t = wave; t < 2 * ntn; t += kFWaves) {
         const int tm = t & 1, tn = t >> 1;
-        const f32x4 y = fused_layer3<H>(S, params, o, d_out, tm, tn, lane);
+        const f32x4 y = fused_layer3<H, false>(S, params, w, o, d_out, tm, tn, lane);
         const int n = 16 * tn + (lane & 15);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -190,7 +255,7 @@ template <int H>
 __global__ void __launch_bounds__(kFThreads)
 k_mlp_train_chunk(const float* __restrict__ params, int d_in, int d_out, const float* __restrict__ X,
                   const float* __restrict__ T, int x_rows, const int32_t* __restrict__ rows, int batch,
-                  const float* __restrict__ mu, const float* __restrict__ isd, float* __restrict__ pg,
+                  const float* __restrict__ mu, const float* __restrict__ isd, W16 w, float* __restrict__ pg,
                   double* __restrict__ lossp) {
     constexpr int HS = FusedLds<H>::HS;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -200,7 +265,7 @@ k_mlp_train_chunk(const float* __restrict__ params, int d_in, int d_out, const f
     const int row0 = blockIdx.x * kFR, nrows = batch - row0 < kFR ? batch - row0 : kFR;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     float* g = pg + (int64_t)blockIdx.x * o.total;
-    fused_forward_hidden<H>(S, params, o, d_in, X, x_rows, rows, row0, nrows, mu, isd);
+    fused_forward_hidden<H, true>(S, params, w, o, d_in, X, x_rows, rows, row0, nrows, mu, isd);
 
     // layer 3, loss and dY = sin(Y - T) / (batch * d_out); zeros past the batch
     const int ntn = (d_out + 15) / 16;
@@ -209,9 +274,9 @@ k_mlp_train_chunk(const float* __restrict__ params, int d_in, int d_out, const f
     for (int e = tid; e < kFR * kFDS; e += kFThreads) S.dy[e] = to_bf16(0.f);
     for (int e = tid; e < kFDmax * kFRS; e += kFThreads) S.dyT[e] = to_bf16(0.f);
     __syncthreads();
-    for (int t = wave; t < 2 * ntn; t += 4) {
+    for (int t = wave; t < 2 * ntn; t += kFWaves) {
         const int tm = t & 1, tn = t >> 1;
-        const f32x4 y = fused_layer3<H>(S, params, o, d_out, tm, tn, lane);
+        const f32x4 y = fused_layer3<H, true>(S, params, w, o, d_out, tm, tn, lane);
         const int n = 16 * tn + (lane & 15);
         f32x4 d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -233,82 +298,86 @@ k_mlp_train_chunk(const float* __restrict__ params, int d_in, int d_out, const f
     lsum = wave_sum(lsum);
     if (lane == 0) S.loss[wave] = lsum;
     __syncthreads();
-    if (tid == 0) lossp[blockIdx.x] = (S.loss[0] + S.loss[1]) + (S.loss[2] + S.loss[3]);
+    if (tid == 0) {
+        double ls = 0.0;
+        for (int w = 0; w < kFWaves; ++w) ls += S.loss[w];
+        lossp[blockIdx.x] = ls;
+    }
     for (int n = tid; n < d_out; n += kFThreads) g[o.b3 + n] = S.colsum[0][n] + S.colsum[1][n];
 
-    // dW3 = dY^T h2 (contraction over the chunk's rows: one step)
-    for (int t = wave; t < ntn * (H / 16); t += 4) {
-        const int tm = t % ntn, tn = t / ntn;  // tm over d_out, tn over H
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mfma(frag_lds(S.dyT, kFRS, 16 * tm, 0, lane), frag_lds(S.h2T, kFRS, 16 * tn, 0, lane), acc);
-        const int n = 16 * tn + (lane & 15);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int d = 16 * tm + 4 * (lane >> 4) + i;
-            if (d < d_out) g[o.W3 + (int64_t)d * H + n] = acc[i];
-        }
-    }
-    __syncthreads();  // the colsum buffer and h2T are reused below
-
-    // dZ2 = (dY W3) * [h2 > 0]; written over h2 (each element read and
-    // written by the lane that owns it) and as dz2T
+    // dZ2 = (dY W3) * [h2 > 0] (written over h2, each element read and
+    // written by the lane that owns it, and as dz2T; column sums for b2 into
+    // cs2), beside dW3 = dY^T h2 (contraction over the chunk's rows: one
+    // step); the longer dZ2 tiles come first
     const int kd = (d_out + 31) / 32 * 32;
-    for (int t = wave; t < 2 * (H / 16); t += 4) {
-        const int tm = t & 1, tn = t >> 1;
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        for (int k0 = 0; k0 < kd; k0 += 32)
-            acc = mfma(frag_lds(S.dy, kFDS, 16 * tm, k0, lane), frag_wt(params + o.W3, H, H, d_out, 16 * tn, k0, lane),
-                       acc);
-        const int n = 16 * tn + (lane & 15);
+    const int tz = 2 * (H / 16);
+    for (int t = wave; t < tz + ntn * (H / 16); t += kFWaves) {
+        if (t < tz) {
+            const int tm = t & 1, tn = t >> 1;
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            for (int k0 = 0; k0 < kd; k0 += 32)
+                acc = mfma(frag_lds(S.dy, kFDS, 16 * tm, k0, lane), frag_g(w.w3t, kFDmax, 16 * tn, k0, lane), acc);
+            const int n = 16 * tn + (lane & 15);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = 16 * tm + 4 * (lane >> 4) + i;
-            const bool on = (float)S.h2[r * HS + n] > 0.f;
-            acc[i] = on ? acc[i] : 0.f;
-            const __bf16 q = to_bf16(acc[i]);
-            S.h2[r * HS + n] = q;
-            S.dz2T[n * kFRS + r] = q;
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * tm + 4 * (lane >> 4) + i;
+                const bool on = (float)S.h2[r * HS + n] > 0.f;
+                acc[i] = on ? acc[i] : 0.f;
+                const __bf16 q = to_bf16(acc[i]);
+                S.h2[r * HS + n] = q;
+                S.dz2T[n * kFRS + r] = q;
+            }
+            const float cs = tile_colsum(acc);
+            if (lane < 16) S.cs2[tm][n] = cs;
+        } else {
+            const int u = t - tz, tm = u % ntn, tn = u / ntn;  // tm over d_out, tn over H
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            acc = mfma(frag_lds(S.dyT, kFRS, 16 * tm, 0, lane), frag_lds(S.h2T, kFRS, 16 * tn, 0, lane), acc);
+            const int n = 16 * tn + (lane & 15);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int d = 16 * tm + 4 * (lane >> 4) + i;
+                if (d < d_out) g[o.W3 + (int64_t)d * H + n] = acc[i];
+            }
         }
-        const float cs = tile_colsum(acc);
-        if (lane < 16) S.colsum[tm][n] = cs;
     }
     __syncthreads();
-    for (int n = tid; n < H; n += kFThreads) g[o.b2 + n] = S.colsum[0][n] + S.colsum[1][n];
+    for (int n = tid; n < H; n += kFThreads) g[o.b2 + n] = S.cs2[0][n] + S.cs2[1][n];
 
-    // dW2 = dZ2^T h1
-    for (int t = wave; t < (H / 16) * (H / 16); t += 4) {
-        const int tm = t % (H / 16), tn = t / (H / 16);
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mfma(frag_lds(S.dz2T, kFRS, 16 * tm, 0, lane), frag_lds(S.h1T, kFRS, 16 * tn, 0, lane), acc);
-        const int n = 16 * tn + (lane & 15);
+    // dZ1 = (dZ2 W2) * [h1 > 0] as dZ1^T over h2T (h2T was last read by dW3;
+    // column sums for b1 into colsum), beside dW2 = dZ2^T h1
+    for (int t = wave; t < tz + (H / 16) * (H / 16); t += kFWaves) {
+        if (t < tz) {
+            const int tm = t & 1, tn = t >> 1;
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int i = 0; i < 4; ++i) g[o.W2 + (int64_t)(16 * tm + 4 * (lane >> 4) + i) * H + n] = acc[i];
-    }
-    __syncthreads();  // the colsum buffer is reused below
-
-    // dZ1 = (dZ2 W2) * [h1 > 0], as dZ1^T over h2T
-    for (int t = wave; t < 2 * (H / 16); t += 4) {
-        const int tm = t & 1, tn = t >> 1;
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        for (int k0 = 0; k0 < H; k0 += 32)
-            acc = mfma(frag_lds(S.h2, HS, 16 * tm, k0, lane), frag_wt(params + o.W2, H, H, H, 16 * tn, k0, lane), acc);
-        const int n = 16 * tn + (lane & 15);
+            for (int k0 = 0; k0 < H; k0 += 32)
+                acc = mfma(frag_lds(S.h2, HS, 16 * tm, k0, lane), frag_g(w.w2t, H, 16 * tn, k0, lane), acc);
+            const int n = 16 * tn + (lane & 15);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = 16 * tm + 4 * (lane >> 4) + i;
-            const bool on = (float)S.h1[r * HS + n] > 0.f;
-            acc[i] = on ? acc[i] : 0.f;
-            S.h2T[n * kFRS + r] = to_bf16(acc[i]);
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * tm + 4 * (lane >> 4) + i;
+                const bool on = (float)S.h1[r * HS + n] > 0.f;
+                acc[i] = on ? acc[i] : 0.f;
+                S.h2T[n * kFRS + r] = to_bf16(acc[i]);
+            }
+            const float cs = tile_colsum(acc);
+            if (lane < 16) S.colsum[tm][n] = cs;
+        } else {
+            const int u = t - tz, tm = u % (H / 16), tn = u / (H / 16);
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            acc = mfma(frag_lds(S.dz2T, kFRS, 16 * tm, 0, lane), frag_lds(S.h1T, kFRS, 16 * tn, 0, lane), acc);
+            const int n = 16 * tn + (lane & 15);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) g[o.W2 + (int64_t)(16 * tm + 4 * (lane >> 4) + i) * H + n] = acc[i];
         }
-        const float cs = tile_colsum(acc);
-        if (lane < 16) S.colsum[tm][n] = cs;
     }
     __syncthreads();
     for (int n = tid; n < H; n += kFThreads) g[o.b1 + n] = S.colsum[0][n] + S.colsum[1][n];
 
     // dW1 = dZ1^T X
     const int nti = (d_in + 15) / 16;
-    for (int t = wave; t < (H / 16) * nti; t += 4) {
+    for (int t = wave; t < (H / 16) * nti; t += kFWaves) {
         const int tm = t % (H / 16), tn = t / (H / 16);
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         acc = mfma(frag_lds(S.h2T, kFRS, 16 * tm, 0, lane), frag_lds(S.xT, kFRS, 16 * tn, 0, lane), acc);
@@ -371,12 +440,12 @@ static bool fused_shape(const dvq_mlp_shape& s) {
 
 template <int H>
 static dvq_status launch_train_chunks(const dvq_mlp_shape& s, const float* params, const float* X, const float* T,
-                                      int x_rows, const int32_t* rows, int batch, const float* mu, const float* isd, float* pg,
-                                      double* lossp, hipStream_t hs) {
+                                      int x_rows, const int32_t* rows, int batch, const float* mu, const float* isd,
+                                      const W16& w, float* pg, double* lossp, hipStream_t hs) {
     const size_t lds = sizeof(FusedLds<H>);
     DVQ_TRY_HIP(allow_lds((const void*)k_mlp_train_chunk<H>, lds));
     hipLaunchKernelGGL(k_mlp_train_chunk<H>, dim3((batch + kFR - 1) / kFR), dim3(kFThreads), lds, hs, params, s.d_in,
-                       s.d_out, X, T, x_rows, rows, batch, mu, isd, pg, lossp);
+                       s.d_out, X, T, x_rows, rows, batch, mu, isd, w, pg, lossp);
     DVQ_CHECK_LAUNCH("k_mlp_train_chunk");
     return DVQ_OK;
 }
@@ -401,7 +470,9 @@ extern "C" {
 size_t dvq_mlp_train_workspace_bytes(const dvq_mlp_shape* s, int32_t batch) {
     if (!s || batch < 1) return 0;
     const int64_t chunks = (batch + kFR - 1) / kFR;
-    return (size_t)chunks * (size_t)offsets(*s).total * sizeof(float) + (size_t)chunks * sizeof(double);
+    const size_t part = ((size_t)chunks * (size_t)offsets(*s).total * sizeof(float) + (size_t)chunks * sizeof(double) +
+                         255) / 256 * 256;
+    return part + w16_elems(s->hidden) * sizeof(__bf16);
 }
 
 dvq_status dvq_mlp_train_step(const dvq_mlp_shape* shape, float* params, float* m, float* v, int32_t t, float lr,
@@ -425,13 +496,19 @@ dvq_status dvq_mlp_train_step(const dvq_mlp_shape* shape, float* params, float* 
     const int chunks = (batch + kFR - 1) / kFR;
     float* pg = static_cast<float*>(workspace);
     double* lossp = reinterpret_cast<double*>(static_cast<char*>(workspace) + (size_t)chunks * count * sizeof(float));
+    const size_t part = ((size_t)chunks * count * sizeof(float) + (size_t)chunks * sizeof(double) + 255) / 256 * 256;
+    const W16 w = w16_layout(static_cast<char*>(workspace) + part, s.hidden);
     hipStream_t hs = stream_of(stream);
+    const int64_t welems = (int64_t)w16_elems(s.hidden);
+    hipLaunchKernelGGL(k_mlp_weights_bf16, dim3((unsigned)((welems + 255) / 256 < 1024 ? (welems + 255) / 256 : 1024)),
+                       dim3(256), 0, hs, params, s.hidden, s.d_in, s.d_out, w);
+    DVQ_CHECK_LAUNCH("k_mlp_weights_bf16");
     if (s.hidden == 64)
-        st = launch_train_chunks<64>(s, params, X, T, x_rows, rows, batch, feat_mean, feat_inv_std, pg, lossp, hs);
+        st = launch_train_chunks<64>(s, params, X, T, x_rows, rows, batch, feat_mean, feat_inv_std, w, pg, lossp, hs);
     else if (s.hidden == 128)
-        st = launch_train_chunks<128>(s, params, X, T, x_rows, rows, batch, feat_mean, feat_inv_std, pg, lossp, hs);
+        st = launch_train_chunks<128>(s, params, X, T, x_rows, rows, batch, feat_mean, feat_inv_std, w, pg, lossp, hs);
     else
-        st = launch_train_chunks<256>(s, params, X, T, x_rows, rows, batch, feat_mean, feat_inv_std, pg, lossp, hs);
+        st = launch_train_chunks<256>(s, params, X, T, x_rows, rows, batch, feat_mean, feat_inv_std, w, pg, lossp, hs);
     if (st != DVQ_OK) return st;
     const float c1 = 1.f - powf(beta1, (float)t), c2 = 1.f - powf(beta2, (float)t);
     const int64_t blocks = (count + 255) / 256 < 1024 ? (count + 255) / 256 : 1024;

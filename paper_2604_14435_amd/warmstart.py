@@ -122,7 +122,7 @@ class WarmStartMLP:
     """d_in -> hidden -> hidden -> P network on the bfloat16 matrix cores.
 
     Training and inference run the fused kernels (dvq_mlp_train_step: one
-    minibatch step in two launches; dvq_mlp_predict): the input
+    minibatch step in three launches; dvq_mlp_predict): the input
     standardisation statistics are computed by the library
     (dvq_feature_stats) and applied inside the kernels; Python only draws
     the epoch's row permutation (host generator) and orders the calls."""
