@@ -218,9 +218,29 @@ def mlp_timing(api, dev, d_in=2, H=256, D=40, B=256, family=4096, reps=200):
     def infer(_):
         api.mlp_forward(shape, params, Xf, out=ffam)
 
+    # fused forms: one training step = 2 launches (rows of a 3584-row
+    # training set picked by an index array, inputs standardised on the
+    # device), one forward pass = 1 launch
+    Xtr = torch.randn(3584, d_in, generator=g).to(dev)
+    Ttr = torch.randn(3584, D, generator=g).to(dev)
+    rows = torch.randperm(3584, generator=g)[:B].to(torch.int32).to(dev)
+    stats = api.feature_stats(Xtr)
+    tws = api.TrainWorkspace(shape, B, dev)
+    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    yfam = api.mlp_predict(shape, params, Xf, stats=stats)
+
+    def train_fused(t):
+        api.mlp_train_step(shape, params, m, v, t, Xtr, Ttr, rows=rows, stats=stats, lr=1e-4, workspace=tws,
+                           loss=loss)
+
+    def infer_fused(_):
+        api.mlp_predict(shape, params, Xf, stats=stats, out=yfam)
+
     res = {}
     for name, fn, flops in (("training_step_b256", train, mlp_flops(B, d_in, H, D, True)),
-                            ("forward_b4096", infer, mlp_flops(family, d_in, H, D, False))):
+                            ("forward_b4096", infer, mlp_flops(family, d_in, H, D, False)),
+                            ("training_step_b256_fused", train_fused, mlp_flops(B, d_in, H, D, True)),
+                            ("forward_b4096_fused", infer_fused, mlp_flops(family, d_in, H, D, False))):
         for t in range(10):
             fn(t + 1)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -236,6 +256,8 @@ def mlp_timing(api, dev, d_in=2, H=256, D=40, B=256, family=4096, reps=200):
                      "mfma_utilisation": round(tf / BF16_MFMA_PEAK, 6)}
     res["peak_tflops"] = BF16_MFMA_PEAK
     res["shape"] = f"{d_in}->{H}->{H}->{D}, bfloat16 operands, float32 accumulation"
+    res["kernels"] = {"unfused": "k_gemm_bf16 per GEMM, k_loss_grad, k_colsum, k_adamw (>= 8 launches per step)",
+                      "fused": "k_mlp_train_chunk (32 rows per workgroup) + k_mlp_reduce_adamw; k_mlp_predict"}
     return res
 
 
@@ -348,8 +370,8 @@ def warm_start_experiment(api, dev, n, layers, eta, budget, epochs, family_iters
     import numpy as np
     import torch
 
-    from paper_2604_14435_amd.warmstart import (MLPConfig, WarmStartMLP, decompose_batches, decompose_family,
-                                                iterations_to, solve, toeplitz_batches)
+    from paper_2604_14435_amd.warmstart import (MLPConfig, WarmStartMLP, choose_start, decompose_batches,
+                                                decompose_family, iterations_to, solve, toeplitz_batches)
     from workloads import family_split, theta_uniform, toeplitz, toeplitz_family
 
     an = api.AnsatzSpec(n, layers, "cz")
@@ -378,10 +400,34 @@ def warm_start_experiment(api, dev, n, layers, eta, budget, epochs, family_iters
     ct, st = coeffs[te].contiguous(), strings[te].contiguous()
     _, hr = solve(an, ct, st, rand, budget, eta)
     _, hw = solve(an, ct, st, pred, budget, eta)
+    # the deployed rule: the prediction, or the random start where the
+    # prediction's cost is not finite or worse than the random start's
+    chosen, used = choose_start(an, ct, st, pred, rand)
+    _, hc = solve(an, ct, st, chosen, budget, eta)
     thr = torch.clamp(hr[-1] + 1e-4, min=1e-4)
     itr = iterations_to(hr, thr).cpu().numpy()
     itw = iterations_to(hw, thr).cpu().numpy()
+    itc = iterations_to(hc, thr).cpu().numpy()
     reached_w = itw >= 0
+    # seconds per system: iterations x the measured time of one iteration of
+    # one system (complex64 adjoint + update, one row per launch)
+    th1 = rand[:1].clone()
+    g1 = torch.empty_like(th1)
+    C1 = torch.empty(1, dtype=torch.float64, device=dev)
+    for _ in range(20):
+        api.vqls_grad_adjoint(an, th1, ct[:1], st[:1], "local", "f32", per_row_system=True, out=(C1, g1))
+        api.gd_step(th1, g1, eta)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(200):
+        api.vqls_grad_adjoint(an, th1, ct[:1], st[:1], "local", "f32", per_row_system=True, out=(C1, g1))
+        api.gd_step(th1, g1, eta)
+    torch.cuda.synchronize()
+    it_s = (time.perf_counter() - t1) / 200
+    t_pred = time.perf_counter()
+    net.predict(ab[te[:1]])
+    torch.cuda.synchronize()
+    t_pred = time.perf_counter() - t_pred
     stats = {
         "systems": {"train": int(len(tr)), "held_out": int(len(te))},
         "budget_iters": budget,
@@ -390,7 +436,17 @@ def warm_start_experiment(api, dev, n, layers, eta, budget, epochs, family_iters
         "median_cost_after_budget": {"random": float(hr[-1].median()), "mlp": float(hw[-1].median())},
         "median_iters_to_threshold": {"random": float(np.median(itr)),
                                       "mlp_reached": float(np.median(itw[reached_w])) if reached_w.any() else None},
-        "fraction_reaching_threshold": {"random": float(np.mean(itr >= 0)), "mlp": float(np.mean(reached_w))},
+        "fraction_reaching_threshold": {"random": float(np.mean(itr >= 0)), "mlp": float(np.mean(reached_w)),
+                                        "mlp_with_fallback": float(np.mean(itc >= 0))},
+        "fallback": {"rule": "prediction unless its cost is not finite or above the random start's",
+                     "prediction_used": float(used.float().mean()),
+                     "median_iters_to_threshold": float(np.median(itc[itc >= 0])) if (itc >= 0).any() else None},
+        "seconds_to_threshold_per_system": {
+            "what": "iterations x one single-system iteration (complex64 adjoint + update, %.1f us)" % (it_s * 1e6),
+            "random_median": round(float(np.median(itr[itr >= 0])) * it_s, 5) if (itr >= 0).any() else None,
+            "mlp_with_fallback_median": round(float(np.median(itc[itc >= 0])) * it_s + t_pred, 5)
+            if (itc >= 0).any() else None,
+            "mlp_prediction_s": round(t_pred, 5)},
         "mlp_loss": {"first_epoch": float(losses[0]), "last_epoch": float(losses[-1])},
         "seconds": {"decompose_family": round(t_dec, 3), "generate_training_angles": round(t_data, 3),
                     "train_mlp": round(t_train, 3)},
@@ -398,11 +454,16 @@ def warm_start_experiment(api, dev, n, layers, eta, budget, epochs, family_iters
     return stats, net
 
 
-def time_to_solution(api, dev, an, coeffs, strings, theta_rand, fast_s, plain_s, budget):
-    """Seconds to solution on the benchmark system: plain form = complex128
-    circuits + shift-rule gradient from random initialisation; fast form =
-    complex64 circuits + adjoint gradient from the learned warm start (random
-    initialisation as the fallback).  The iteration counts come from the
+def gd_plateau_comparison(api, dev, an, coeffs, strings, theta_rand, fast_s, plain_s, budget):
+    """Gradient descent (the workloads' optimizer) on the benchmark system,
+    CZ ladder, 4 layers: seconds until the cost reaches the plateau the plain
+    form reaches from random initialisation within the budget (+ 1e-4).
+    Plain form = complex128 circuits + shift-rule gradient from random
+    initialisation; fast form = complex64 circuits + adjoint gradient from
+    the learned warm start (random initialisation as the fallback).  Both
+    runs end on the same plateau, far from the solution (the fidelities at
+    the threshold are reported): this is not a time to solution (that is
+    fidelity_target).  The iteration counts come from the
     exact-gradient trajectories (the shift rule and the float64 adjoint give
     the same gradient to ~1e-12, checked on the first iterations below); the
     seconds are those counts times the measured per-iteration times."""
@@ -459,14 +520,14 @@ def time_to_solution(api, dev, an, coeffs, strings, theta_rand, fast_s, plain_s,
                                     "seconds": round(it_fast * fast_s + t_predict, 4) if it_fast >= 0 else None},
         "trajectory_check_shift_vs_adjoint_3_iters": traj_dev,
         "final_cost": {"plain": float(h_plain[-1, 0]), "fast": float(h_fast[-1, 0])},
-        "fidelity": fids,
+        "fidelity_at_threshold": fids,
+        "note": "both runs stop on the gradient-descent plateau C_L ~ 0.1 of this ansatz (CZ ladder, 4 layers): "
+                "a time to a shared plateau, not to a solution; time_to_solution is the fidelity run",
         "method": "iterations on the exact-gradient trajectories x measured seconds per iteration",
     }
     if it_plain >= 0 and it_fast >= 0:
         tts["speedup"] = round((it_plain * plain_s) / (it_fast * fast_s + t_predict), 1)
-    tts["lbfgs"] = lbfgs_study(api, dev, an, coeffs, strings, theta_rand, net, plain_s)
-    tts["lbfgs_cnot"] = cnot_fidelity_study(api, dev, coeffs, strings)
-    return stats, tts
+    return stats, tts, net
 
 
 def lbfgs_study(api, dev, an, coeffs, strings, theta_rand, net, plain_s, max_evals=3000):
@@ -531,60 +592,165 @@ def lbfgs_study(api, dev, an, coeffs, strings, theta_rand, net, plain_s, max_eva
             "runs": runs}
 
 
-def cnot_fidelity_study(api, dev, coeffs, strings, max_evals=4000):
-    """Fidelity >= 0.999 at n = 10, L = 64: the bench system with the RY +
-    CNOT-ladder ansatz (4 layers; the CZ ladder cannot exceed F ~ 0.989),
-    local cost, both forms from the angles with V(theta)|0> = b (first layer
-    pi/2, the rest 0), L-BFGS-B.  Plain: float64 shift rule (evaluation
-    counts from the float64 adjoint, which gives the same costs, charged the
-    measured shift-rule time per evaluation).  Fast: complex64 circuits +
-    adjoint until the float32 cost stops resolving the steps, then
-    complex128 adjoint refinement (wall clock)."""
+FID_LAYERS, FID_TARGET = 8, 0.9999
+FID_RECORD = os.path.join(ROOT, "profiles", "fidelity_n10_L64_cnot8_local.json")
+
+
+def fidelity_target(api, dev, coeffs, strings, max_evals=4000, family_bins=16, family_iters=100, epochs=300):
+    """Seconds to fidelity 0.9999 against x~ = A~^-1 b on the bench system
+    (n = 10, L = 64), RY + CNOT ladder, 8 layers, local cost, L-BFGS-B.
+
+    plain form: float64 shift rule.  Its per-evaluation time is measured
+      here (graph replay, 161 x 90,112 circuits); its evaluation count to the
+      target comes from the float64 adjoint trajectory (the same costs and
+      gradients to rounding) from the same start.  The same run timed end to
+      end by wall clock is bench_fidelity.py's (recorded in profiles/).
+    fast forms (wall clock): complex64 adjoint (with and without the
+      complex64 circuits for the cost), continued with the complex128
+      adjoint when the float32 phase stops; from the start V|0> = b, and
+      from the learned warm start: an MLP (2 -> 256 -> 256 -> 80, bfloat16
+      matrix cores) trained on the Toeplitz family (4096 systems, top-64
+      terms) whose targets come from the solver itself by continuation in
+      b (the centre system solved from V|0> = b; the family in 16 bins of b
+      taken outward from the centre, each system started from the nearest
+      solved system and each bin solved by one batched L-BFGS run on the
+      complex128 adjoint), with V|0> = b as the fallback."""
     import numpy as np
     import torch
 
     from paper_2604_14435_amd.optim import Evaluator, lbfgs, lbfgs_refine
-    from workloads import plus_state
+    from paper_2604_14435_amd.warmstart import (MLPConfig, WarmStartMLP, continuation_targets, decompose_batches,
+                                                decompose_family, toeplitz_batches)
+    from workloads import family_split, plus_state, toeplitz, toeplitz_family
 
     n = N_QUBITS
-    an = api.AnsatzSpec(n, LAYERS, "cnot")
+    an = api.AnsatzSpec(n, FID_LAYERS, "cnot")
+    kind = "local"
     At = api.pauli_sum_dense(coeffs, strings, n).real.cpu().numpy()
-    xs = np.linalg.solve(At, plus_state(n))
-    tgt = torch.from_numpy((xs / np.linalg.norm(xs)).astype(np.complex128)).to(dev)
-    th0 = np.zeros(an.P)
-    th0[:n] = np.pi / 2
-    ev_ps = Evaluator(an, coeffs, strings, "f64")
-    ev_ps(th0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(3):
-        ev_ps(th0)
-    ps_eval_s = (time.perf_counter() - t0) / 3
-    thresholds = (0.99, 0.999)
+    bvec = plus_state(n)
+    xt = np.linalg.solve(At, bvec)
+    xt /= np.linalg.norm(xt)
+    xf = np.linalg.solve(toeplitz(n, DIAG, OFFDIAG), bvec)
+    xf /= np.linalg.norm(xf)
+    tgt = torch.from_numpy(xt.astype(np.complex128)).to(dev)
+    th_b = np.zeros(an.P)
+    th_b[:n] = np.pi / 2
+    thresholds = (0.99, 0.999, FID_TARGET)
 
-    def first(tr, secs):
-        F = api.fidelity(an, torch.from_numpy(np.stack([th0] + tr.thetas)).to(dev), tgt).cpu().numpy()
+    def fid(thetas):
+        return api.fidelity(an, torch.from_numpy(np.stack(thetas)).to(dev), tgt).cpu().numpy()
+
+    def reach(F, secs, evs):
         out = {}
         for thr in thresholds:
             idx = np.nonzero(F >= thr)[0]
-            out[str(thr)] = round(float(secs[idx[0]]), 4) if len(idx) else None
-        return out, float(F[-1]), float(F.max())
+            out[str(thr)] = ({"seconds": round(float(secs[idx[0]]), 4), "evaluations": int(evs[idx[0]])}
+                             if len(idx) else None)
+        return out
 
-    _, tp = lbfgs(Evaluator(an, coeffs, strings, "f64-adjoint"), th0, max_evals=max_evals, gtol=1e-12)
-    reach_p, fp, fpm = first(tp, [0.0] + list(np.array(tp.iter_evals) * ps_eval_s))
-    _, tf = lbfgs_refine(Evaluator(an, coeffs, strings, "f32"), Evaluator(an, coeffs, strings, "f64-adjoint"), th0,
-                         max_evals=max_evals, gtol=1e-12)
-    reach_f, ff, ffm = first(tf, [0.0] + tf.iter_seconds)
-    out = {"system": "toeplitz_n10_L64 (a=1.0, b=-0.45), RY+CNOT ladder, 4 layers, local cost, start V|0> = b",
-           "plain_seconds_per_evaluation": round(ps_eval_s, 5),
-           "plain_fp64_shift": {"evaluations": tp.evals, "seconds_to_fidelity": reach_p, "final_fidelity": fp,
-                                "max_fidelity": fpm, "final_cost": min(tp.costs)},
-           "fp32_adjoint_then_fp64_refine": {"evaluations": tf.evals, "seconds_to_fidelity": reach_f,
-                                             "final_fidelity": ff, "max_fidelity": ffm, "final_cost": min(tf.costs),
-                                             "stop": tf.stop}}
-    a, b = reach_p.get("0.999"), reach_f.get("0.999")
-    if a and b:
-        out["speedup_to_0.999"] = round(a / b, 1)
+    def run_fast(form, th0, t_extra=0.0):
+        fast = Evaluator(an, coeffs, strings, form, kind=kind)
+        precise = Evaluator(an, coeffs, strings, "f64-adjoint", kind=kind)
+        fast(th0), precise(th0)  # graphs captured before the clock starts
+        th, tr = lbfgs_refine(fast, precise, th0, max_evals=max_evals, gtol=1e-12)
+        F = fid([th0] + tr.thetas)
+        return {"evaluations": tr.evals, "seconds": round(tr.seconds + t_extra, 4),
+                "reach": reach(F, [t_extra] + [x + t_extra for x in tr.iter_seconds], [0] + tr.iter_evals),
+                "start_fidelity": float(F[0]), "final_fidelity": float(F[-1]), "stop": tr.stop[:80]}
+
+    out = {"system": "toeplitz_n10_L64 (a=1.0, b=-0.45), RY+CNOT ladder, %d layers (%d angles), local cost"
+                     % (FID_LAYERS, an.P),
+           "target_fidelity": FID_TARGET, "against": "x~ = A~^-1 b (the pruned system)",
+           "fidelity_pruned_vs_full_solution": float(abs(np.dot(xt, xf)) ** 2),
+           "optimizer": "L-BFGS-B (SciPy, host), at most %d evaluations" % max_evals}
+    # plain form
+    plain = Evaluator(an, coeffs, strings, "f64", kind=kind)
+    plain(th_b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        plain(th_b)
+    plain_eval_s = (time.perf_counter() - t0) / 3
+    ad64 = Evaluator(an, coeffs, strings, "f64-adjoint", kind=kind)
+    c_ps, c_ad = plain(th_b)[0], ad64(th_b)[0]
+    _, tr = lbfgs(ad64, th_b, max_evals=max_evals, gtol=1e-12)
+    F = fid([th_b] + tr.thetas)
+    r = reach(F, [0.0] + list(np.array(tr.iter_evals) * plain_eval_s), [0] + tr.iter_evals)
+    out["plain_fp64_shift_from_b"] = {
+        "seconds_per_evaluation": round(plain_eval_s, 5),
+        "circuits_per_evaluation": (2 * an.P + 1) * api.circuit_count(n, coeffs.shape[0], kind),
+        "reach_modelled": r, "method": "evaluations of the float64 adjoint trajectory x measured seconds per "
+                                       "shift-rule evaluation", "first_cost_shift_minus_adjoint": c_ps - c_ad}
+    if os.path.exists(FID_RECORD):
+        with open(FID_RECORD) as f:
+            rec = json.load(f)
+        out["plain_fp64_shift_from_b"]["wall_clock_recorded"] = {
+            "source": "profiles/" + os.path.basename(FID_RECORD) + " (bench_fidelity.py, one MI355X)",
+            **{k: rec.get("plain_fp64_shift", {}).get(k) for k in ("reach", "wall_seconds", "evaluations",
+                                                                  "seconds_per_evaluation")}}
+    # fast forms from the same start
+    out["fp32_adjoint_from_b"] = run_fast("f32-adjoint", th_b)
+    out["fp32_circuits_adjoint_from_b"] = run_fast("f32", th_b)
+    # learned warm start (one-off: family, targets, training)
+    t0 = time.perf_counter()
+    ab = toeplitz_family(4096, seed=0)
+    fc, fs, _ = decompose_batches(toeplitz_batches(ab, n, dev), 64)
+    c0, s0, _ = decompose_family([toeplitz(n, 1.0, -0.3)], 64, dev)
+    th_c, _ = lbfgs(Evaluator(an, c0[0], s0[0], "f64-adjoint", kind=kind), th_b, max_evals=6000, gtol=1e-12)
+    targets, fcost = continuation_targets(an, ab, fc, fs, th_c, (1.0, -0.3), bins=family_bins, iters=family_iters)
+    t_targets = time.perf_counter() - t0
+    tr_idx, te_idx = family_split(len(ab), 3584, seed=1)
+    keep = tr_idx[fcost[tr_idx] <= 5.0 * np.median(fcost)]
+    t0 = time.perf_counter()
+    net = WarmStartMLP(2, an.P, MLPConfig(hidden=256, epochs=epochs, batch=256, lr=1e-3), dev)
+    losses = net.fit(ab[keep], torch.from_numpy(targets[keep]).to(dev))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    # per system: predict, choose between the prediction and V|0> = b by
+    # cost (complex64 adjoint), then the fast form
+    chooser = Evaluator(an, coeffs, strings, "f32-adjoint", kind=kind)
+    chooser(th_b)
+    t0 = time.perf_counter()
+    pred = net.predict(np.array([[DIAG, OFFDIAG]]))[0].cpu().numpy()
+    use_pred = chooser(pred)[0] <= chooser(th_b)[0]
+    t_choose = time.perf_counter() - t0
+    if use_pred:
+        out["fp32_adjoint_warm_start"] = run_fast("f32-adjoint", pred, t_extra=t_choose)
+        out["fp32_circuits_adjoint_warm_start"] = run_fast("f32", pred, t_extra=t_choose)
+    else:  # the selection kept V|0> = b: the runs from_b plus the selection time
+        for key, src in (("fp32_adjoint_warm_start", "fp32_adjoint_from_b"),
+                         ("fp32_circuits_adjoint_warm_start", "fp32_circuits_adjoint_from_b")):
+            r0 = out[src]
+            out[key] = {**r0, "seconds": round(r0["seconds"] + t_choose, 4),
+                        "reach": {k: (None if v is None else {**v, "seconds": round(v["seconds"] + t_choose, 4)})
+                                  for k, v in r0["reach"].items()},
+                        "start": "V|0> = b (the selection kept it); the %s run plus the selection" % src}
+    # the same choice on 64 held-out systems of the family (costs only)
+    held = te_idx[:64]
+    hp = net.predict(ab[held]).cpu().numpy()
+    hb = np.tile(th_b, (len(held), 1))
+    from paper_2604_14435_amd.optim import BatchEvaluator
+    bev = BatchEvaluator(an, fc[torch.from_numpy(held).to(dev)].contiguous(),
+                         fs[torch.from_numpy(held).to(dev)].contiguous(), "f32", kind)
+    cp_, cb_ = bev(hp)[0], bev(hb)[0]
+    out["warm_start"] = {"prediction_used": bool(use_pred), "prediction_fidelity": float(fid([pred])[0]),
+                         "start_fidelity_b": float(fid([th_b])[0]),
+                         "held_out_64": {"prediction_chosen": float(np.mean(cp_ <= cb_)),
+                                         "median_cost_prediction": float(np.median(cp_)),
+                                         "median_cost_b_start": float(np.median(cb_))},
+                         "predict_and_choose_s": round(t_choose, 5),
+                         "one_off_s": {"family_and_targets": round(t_targets, 3), "train_mlp": round(t_train, 3)},
+                         "family": {"systems": len(ab), "targets": "continuation in b: %d bins, batched L-BFGS "
+                                    "(%d iterations per bin, complex128 adjoint)" % (family_bins, family_iters),
+                                    "train_rows_kept": int(len(keep)), "train_rows": int(len(tr_idx)),
+                                    "median_target_cost": float(np.median(fcost))},
+                         "mlp_loss": {"first_epoch": float(losses[0]), "last_epoch": float(losses[-1])}}
+    plain_t = r.get(str(FID_TARGET))
+    for key in ("fp32_adjoint_from_b", "fp32_circuits_adjoint_from_b", "fp32_adjoint_warm_start",
+                "fp32_circuits_adjoint_warm_start"):
+        ft = out[key]["reach"].get(str(FID_TARGET))
+        if plain_t and ft:
+            out[key]["speedup_vs_plain_modelled"] = round(plain_t["seconds"] / ft["seconds"], 1)
     return out
 
 
@@ -1141,9 +1307,12 @@ def main() -> int:
         out["heleshaw"] = heleshaw_run(api, dev)
         progress("Hele-Shaw-like system done")
     if not args.no_warmstart:
-        out["warm_start"], out["time_to_solution"] = time_to_solution(
+        out["time_to_solution"] = fidelity_target(api, dev, coeffs, strings)
+        progress("time to fidelity 0.9999 done")
+        out["warm_start"], out["gd_time_to_plain_plateau"], net = gd_plateau_comparison(
             api, dev, an, coeffs, strings, theta0, fast_s, plain_s, args.tts_budget)
-        progress("warm start and time to solution done")
+        out["lbfgs_cz_ladder"] = lbfgs_study(api, dev, an, coeffs, strings, theta0, net, plain_s)
+        progress("warm start and plateau comparisons done")
         out["four_qubit_fidelity"] = four_qubit_fidelity(api, dev)
         progress("four-qubit fidelity run done")
     out["mlp"] = mlp_timing(api, dev)
