@@ -330,7 +330,7 @@ def cpu_baseline(seconds: float, pool_seconds: float, full_limit: float):
             el = time.perf_counter() - t0
             terms = (vals[0::2] + 1j * vals[1::2]).reshape(N_QUBITS + 1, L, L)
             cost = oc.cost_from_terms(_SAMPLE["coeffs"], terms[0], terms[1:], N_QUBITS, "local")
-            full = {"seconds": round(el, 3), "cost": cost}
+            full = {"seconds": round(el, 3), "cost": cost, "beta": terms[0], "delta": terms[1:]}
             rate, done_all = total / el, total
             sample = (f"the whole n=10 L=64 cost evaluation ({total} circuits) and its cost, gate by gate "
                       f"in NumPy float64, {workers} processes, {el:.1f} s")
@@ -347,6 +347,12 @@ def cpu_baseline(seconds: float, pool_seconds: float, full_limit: float):
     del A
     small = small_workload_oracle()
     progress(f"oracle n=3 workload: {small['seconds']:.1f} s")
+    if full is not None:
+        # the exact shift-rule gradient at the same angles, on the dense cost
+        At = op.reconstruct(_SAMPLE["coeffs"], _SAMPLE["xs"], _SAMPLE["zs"], N_QUBITS)
+        parts = lambda t: oc.parts_theta_dense(t, At, N_QUBITS, LAYERS, "cz", "local")
+        full["grad_cost"], full["grad"] = oc.grad_parameter_shift(parts, _SAMPLE["th"], N_QUBITS, "local")
+        progress("oracle gradient done")
     P = N_QUBITS * LAYERS
     out = {"value": round(rate, 2), "unit": "circuits/s", "cores": workers, "kind": "oracle", "sample": sample,
            "cpu_model": _cpu_model(), "nproc": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0)),
@@ -1324,6 +1330,23 @@ def main() -> int:
             cpu["cost_vs_gpu"] = {"oracle": full_oracle["cost"], "gpu_fp64": c64.item(), "gpu_fp32": c32.item(),
                                   "abs_fp64": abs(c64.item() - full_oracle["cost"]),
                                   "abs_fp32": abs(c32.item() - full_oracle["cost"])}
+            # the oracle's terms in the order of the GPU's kept strings
+            pos = {(int(x), int(z)): i for i, (x, z) in enumerate(zip(_SAMPLE["xs"], _SAMPLE["zs"]))}
+            perm = np.array([pos[(int(x), int(z))] for x, z in strings.cpu().numpy()])
+            ob = full_oracle["beta"][np.ix_(perm, perm)]
+            od = full_oracle["delta"][:, perm][:, :, perm]
+            og = full_oracle["grad"]
+            _, gsh = api.vqls_grad_shift(an, theta0, coeffs, strings, "local", "f64")
+            mx = lambda a, b_: float(np.max(np.abs(a.cpu().numpy().reshape(b_.shape) - b_)))
+            out["error_vs_oracle"] = {
+                "what": "max |GPU - oracle| over every term of the n=10 L=64 evaluation at theta0 (4,096 beta and "
+                        "40,960 delta terms, 90,112 oracle circuits), the cost, and the gradient (oracle: exact "
+                        "shift rule on the dense cost)",
+                "beta": {"fp64": mx(b64[0], ob), "fp32": mx(b32[0], ob)},
+                "delta": {"fp64": mx(d64[0], od), "fp32": mx(d32[0], od)},
+                "cost": {"fp64": abs(c64.item() - full_oracle["cost"]), "fp32": abs(c32.item() - full_oracle["cost"])},
+                "gradient": {"plain_fp64_shift": mx(gsh, og), "fp64_adjoint": mx(g64[0], og),
+                             "fp32_adjoint": mx(g32[0], og)}}
         out["cpu_baseline"] = cpu
     print(json.dumps(out))
     return 0

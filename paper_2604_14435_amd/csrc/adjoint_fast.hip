@@ -28,19 +28,19 @@
 
 namespace dvq {
 
-__device__ __forceinline__ float other_half(float x) {
+// The value lane + 32 holds, in lanes 0..31 (lambda next to x; the upper
+// lanes receive the lower half's values, which no caller uses): one
+// v_permlane32_swap.
+__device__ __forceinline__ float from_upper(float x) {
     const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
-    return __uint_as_float((threadIdx.x & 32) ? r[0] : r[1]);
+    return __uint_as_float(r[1]);
 }
 
-__device__ __forceinline__ double other_half(double x) {
+__device__ __forceinline__ double from_upper(double x) {
     const unsigned long long u = (unsigned long long)__double_as_longlong(x);
-    const unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
-    const auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-    const auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-    const bool up = threadIdx.x & 32;
-    const unsigned nlo = up ? rl[0] : rl[1], nhi = up ? rh[0] : rh[1];
-    return __longlong_as_double((long long)(((unsigned long long)nhi << 32) | nlo));
+    const auto rl = __builtin_amdgcn_permlane32_swap((unsigned)u, (unsigned)u, false, false);
+    const auto rh = __builtin_amdgcn_permlane32_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
+    return __longlong_as_double((long long)(((unsigned long long)rh[1] << 32) | rl[1]));
 }
 
 // Re <K_q x | lambda> summed over this lane's pairs of qubit Q, with the
@@ -50,20 +50,20 @@ __device__ __forceinline__ double grad_reg(const T* re, const T* im, int lane) {
     using Ly = Lay<NQ, HI>;
     constexpr int R = Ly::R;
     constexpr int j = Ly::reg(Q);
-    double acc = 0.0;
+    T acc = 0;  // the lane's 2^(n-6) pairs in the state precision, one float64 conversion
 #pragma unroll
     for (int r0 = 0; r0 < R; ++r0) {
         if (r0 & (1 << j)) continue;
         const int r1 = r0 | (1 << j);
-        const T l0r = other_half(re[r0]), l0i = other_half(im[r0]);
-        const T l1r = other_half(re[r1]), l1i = other_half(im[r1]);
+        const T l0r = from_upper(re[r0]), l0i = from_upper(im[r0]);
+        const T l1r = from_upper(re[r1]), l1i = from_upper(im[r1]);
         // (K x)[i0] = -x[i1], (K x)[i1] = x[i0]
         const T v = (re[r0] * l1r + im[r0] * l1i) - (re[r1] * l0r + im[r1] * l0i);
         const bool neg = PAR ? reg_rho<NQ, HI, Q>(r0) : false;
-        acc += neg ? -(double)v : (double)v;
+        acc += neg ? -v : v;
     }
     if (PAR && lane_rho<NQ, HI, Q>(lane)) acc = -acc;
-    return (lane & 32) ? 0.0 : acc;
+    return (lane & 32) ? 0.0 : (double)acc;
 }
 
 // For every register qubit q in [Q, QEND): gradient of RY_q, then undo RY_q.
@@ -92,21 +92,21 @@ __device__ __forceinline__ double grad_reg_ladder(const T* re, const T* im, int 
     static_assert(j >= 0 && (Q + 1 == NQ || jp >= 0), "pair not in registers");
     constexpr int mask = (1 << j) | (jp >= 0 ? (1 << jp) : 0);
     constexpr int low = HI ? ((1 << (Q - 5)) - 1) : ((1 << Q) - 1);
-    double acc = 0.0;
+    T acc = 0;
 #pragma unroll
     for (int r0 = 0; r0 < R; ++r0) {
         if (r0 & (1 << j)) continue;
         const int r1 = r0 ^ mask;
-        const T l0r = other_half(re[r0]), l0i = other_half(im[r0]);
-        const T l1r = other_half(re[r1]), l1i = other_half(im[r1]);
+        const T l0r = from_upper(re[r0]), l0i = from_upper(im[r0]);
+        const T l1r = from_upper(re[r1]), l1i = from_upper(im[r1]);
         // stored r0 is the true |0> member unless the qubits below Q have odd parity
         const T v = (re[r0] * l1r + im[r0] * l1i) - (re[r1] * l0r + im[r1] * l0i);
-        acc += odd_bits(r0 & low) ? -(double)v : (double)v;
+        acc += odd_bits(r0 & low) ? -v : v;
     }
     if constexpr (HI) {
         if (__popc((unsigned)(lane & 31)) & 1) acc = -acc;
     }
-    return (lane & 32) ? 0.0 : acc;
+    return (lane & 32) ? 0.0 : (double)acc;
 }
 
 // For every qubit q in [Q, QEND) (register pairs in the ladder frame):
@@ -131,18 +131,18 @@ __device__ __forceinline__ void grad_undo_lane_ladder_lo(T* re, T* im, int lane,
                                                          double* __restrict__ grad) {
     using Ly = Lay<NQ, false>;
     constexpr int R = Ly::R, j = Ly::RB - 1;
-    double acc = 0.0;
+    T acc = 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (odd_bits(r)) continue;
         const int rp = r ^ (1 << j);
         const T x1r = lane_xor1(re[rp]), x1i = lane_xor1(im[rp]);
-        const T l0r = other_half(re[r]), l0i = other_half(im[r]);
-        const T l1r = other_half(x1r), l1i = other_half(x1i);
+        const T l0r = from_upper(re[r]), l0i = from_upper(im[r]);
+        const T l1r = from_upper(x1r), l1i = from_upper(x1i);
         const T v = (re[r] * l1r + im[r] * l1i) - (x1r * l0r + x1i * l0i);
-        acc += (double)v;
+        acc += v;
     }
-    const double gq = wave_sum((lane & 32) ? 0.0 : acc);
+    const double gq = wave_sum((lane & 32) ? 0.0 : (double)acc);
     if (lane == 0) grad[k] = gq;
     ry_lane_ladder_lo<T, NQ>(re, im, -trig[2 * k], -trig[2 * k + 1]);
 }
