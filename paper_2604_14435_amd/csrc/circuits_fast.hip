@@ -233,15 +233,21 @@ __device__ __forceinline__ T measure_planar(T* re, T* im, T* P, SignedPerm sp, i
     if constexpr (ENT != DVQ_ENT_CZ_LADDER)
         if (layers & 1) relayout_ladder<T, NQ, true>(re, im, P, lane);  // HI ladder frame -> LO true frame
     const SuffixLane sl = suffix_lane(sp, lane);
+    // pad_slot(lane + 64 i) = a0 + 66 i: one base, the offsets are immediates
+    const int a0 = lane + (lane >> 5);
     T a0r[KPL], gr[KPL];
     store_final_plane<T, NQ, ENT>(re, P, layers, lane);
 #pragma unroll
     for (int i = 0; i < KPL; ++i) {
-        a0r[i] = P[pad_slot(lane + 64 * i)];
+        a0r[i] = P[a0 + 66 * i];
         gr[i] = P[suffix_slot(sl, N, i)];
     }
     __syncthreads();  // every lane has read the real parts
     store_final_plane<T, NQ, ENT>(im, P, layers, lane);
+    // The gather addresses are formed again for the imaginary parts (one
+    // add each) instead of being held in registers across the store above.
+    SuffixLane sl2 = sl;
+    asm volatile("" : "+v"(sl2.base));
     // |a0 + a1|^2 - |a0 - a1|^2 = 4 Re(conj(a0) a1), a1 = sgn (c + i d) g:
     // 4 sgn (c (a0r gr + a0i gi) + d (a0i gr - a0r gi)).  One of c, d is zero,
     // the same one in every lane (the lane part of the phase only flips its
@@ -253,7 +259,7 @@ __device__ __forceinline__ T measure_planar(T* re, T* im, T* P, SignedPerm sp, i
     if (!odd) {
 #pragma unroll
         for (int i = 0; i < KPL; ++i) {
-            const T a0i = P[pad_slot(lane + 64 * i)], gi = P[suffix_slot(sl, N, i)];
+            const T a0i = P[a0 + 66 * i], gi = P[suffix_slot(sl2, N, i)];
             const T sgn = (__popc((unsigned)(i & sl.zh)) & 1) ? (T)-1 : (T)1;
             z = fmat(sgn, fmat(a0r[i], gr[i], a0i * gi), z);
         }
@@ -261,7 +267,7 @@ __device__ __forceinline__ T measure_planar(T* re, T* im, T* P, SignedPerm sp, i
     } else {
 #pragma unroll
         for (int i = 0; i < KPL; ++i) {
-            const T a0i = P[pad_slot(lane + 64 * i)], gi = P[suffix_slot(sl, N, i)];
+            const T a0i = P[a0 + 66 * i], gi = P[suffix_slot(sl2, N, i)];
             const T sgn = (__popc((unsigned)(i & sl.zh)) & 1) ? (T)-1 : (T)1;
             z = fmat(sgn, fmat(a0i, gr[i], -(a0r[i] * gi)), z);
         }
