@@ -30,7 +30,7 @@ namespace dvq {
 
 // The value lane + 32 holds, in lanes 0..31 (lambda next to x; the upper
 // lanes receive the lower half's values, which no caller uses): one
-// v_permlane32_swap.
+// v_permlane32_swap per 32-bit word.
 __device__ __forceinline__ float from_upper(float x) {
     const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
     return __uint_as_float(r[1]);
@@ -43,108 +43,177 @@ __device__ __forceinline__ double from_upper(double x) {
     return __longlong_as_double((long long)(((unsigned long long)rh[1] << 32) | rl[1]));
 }
 
-// Re <K_q x | lambda> summed over this lane's pairs of qubit Q, with the
-// lazy-ladder sign when PAR; meaningful in lanes 0..31 (0 in the others).
-template <typename T, int NQ, bool HI, int Q, int PAR>
-__device__ __forceinline__ double grad_reg(const T* re, const T* im, int lane) {
-    using Ly = Lay<NQ, HI>;
-    constexpr int R = Ly::R;
-    constexpr int j = Ly::reg(Q);
-    T acc = 0;  // the lane's 2^(n-6) pairs in the state precision, one float64 conversion
-#pragma unroll
-    for (int r0 = 0; r0 < R; ++r0) {
-        if (r0 & (1 << j)) continue;
-        const int r1 = r0 | (1 << j);
-        const T l0r = from_upper(re[r0]), l0i = from_upper(im[r0]);
-        const T l1r = from_upper(re[r1]), l1i = from_upper(im[r1]);
-        // (K x)[i0] = -x[i1], (K x)[i1] = x[i0]
-        const T v = (re[r0] * l1r + im[r0] * l1i) - (re[r1] * l0r + im[r1] * l0i);
-        const bool neg = PAR ? reg_rho<NQ, HI, Q>(r0) : false;
-        acc += neg ? -v : v;
-    }
-    if (PAR && lane_rho<NQ, HI, Q>(lane)) acc = -acc;
-    return (lane & 32) ? 0.0 : (double)acc;
-}
+// ------------------------------------------------------------ gradient sums
+//
+// dC/dtheta of the RY on qubit q is Re <K_q x | lambda> with (K x)_0 = -x_1,
+// (K x)_1 = x_0 on each amplitude pair of q, i.e. x_0 . lambda_1 - x_1 .
+// lambda_0 per pair (a . b = Re(conj(a) b)).  All RYs of one layer commute
+// with each other's generators, so the gradients of every qubit a layout
+// holds in its registers are taken from the same registers, before any of
+// them is undone.  Lambda is brought to the lower lanes once per range and
+// chunk (R / CH registers at a time, so at most that many extra registers
+// of each component are live); each register r of a chunk then adds, for
+// every qubit, lambda at r times x at its pair partner, negated when r is
+// the pair's |0> member, with the pair's frame sign.  Each lane keeps one
+// partial sum per qubit, written to LDS (gb[q * 33 + lane], lanes 0..31);
+// flush_grad adds the 32 partials of each qubit once per layer, so no
+// cross-lane reduction sits in the sweep's dependency chain.
 
-// For every register qubit q in [Q, QEND): gradient of RY_q, then undo RY_q.
-template <typename T, int NQ, bool HI, int PAR, int Q, int QEND>
-__device__ __forceinline__ void grad_undo_range(T* re, T* im, int lane, const T* trig, int kbase,
-                                                double* __restrict__ grad) {
+template <typename T, int R>
+constexpr int kGradChunks = (int)sizeof(T) * R > 128 ? 2 : 1;
+
+// Pair structure of qubit Q in layout HI: CZ form (partner r ^ 2^j, lazy
+// sign frame when PAR) or ladder frame (partner r ^ 2^j ^ 2^j', j' the
+// register bit of Q + 1, sign from the parity of the qubits below Q).
+template <int NQ, bool HI, int Q, int PAR, bool LADDER>
+struct PairOf {
+    using Ly = Lay<NQ, HI>;
+    static constexpr int j = Ly::reg(Q);
+    static constexpr int jp = (LADDER && Q + 1 < NQ) ? Ly::reg(Q + 1) : -1;
+    static_assert(j >= 0 && (!LADDER || Q + 1 == NQ || jp >= 0), "pair not in registers");
+    static constexpr int mask = (1 << j) | (jp >= 0 ? (1 << jp) : 0);
+    static constexpr int low = !LADDER ? 0 : (HI ? ((1 << (Q - 5)) - 1) : ((1 << Q) - 1));
+    static constexpr int partner(int r) { return r ^ mask; }
+    static constexpr bool one(int r) { return (r >> j) & 1; }
+    static constexpr bool neg(int r) {
+        const int r0 = one(r) ? partner(r) : r;
+        return LADDER ? odd_bits(r0 & low) : (PAR ? reg_rho<NQ, HI, Q>(r0) : false);
+    }
+    // the term of register r enters with + (|1> member) or - (|0> member), times the pair sign
+    static constexpr bool plus(int r) { return one(r) != neg(r); }
+    __device__ static bool lane_neg(int lane) {
+        if constexpr (LADDER)
+            return HI && (__popc((unsigned)(lane & 31)) & 1);
+        else
+            return PAR && lane_rho<NQ, HI, Q>(lane);
+    }
+};
+
+template <typename T, int NQ, bool HI, int PAR, bool LADDER, int Q, int QEND, int C0, int H>
+__device__ __forceinline__ void grad_chunk(const T* re, const T* im, const T* lr, const T* li, T* acc) {
     if constexpr (Q < QEND) {
         if constexpr (Lay<NQ, HI>::reg(Q) >= 0) {
-            const double gq = wave_sum(grad_reg<T, NQ, HI, Q, PAR>(re, im, lane));
-            if (lane == 0) grad[kbase + Q] = gq;
-            const T t = -trig[2 * (kbase + Q)], s = -trig[2 * (kbase + Q) + 1];
-            ry_reg<T, NQ, HI, Q, PAR>(re, im, lane, t, s);
+            using Pr = PairOf<NQ, HI, Q, PAR, LADDER>;
+            T a = acc[Q];
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                const int r = C0 + h, p = Pr::partner(r);
+                a = fmat(Pr::plus(r) ? re[p] : -re[p], lr[h], a);
+                a = fmat(Pr::plus(r) ? im[p] : -im[p], li[h], a);
+            }
+            acc[Q] = a;
         }
-        grad_undo_range<T, NQ, HI, PAR, Q + 1, QEND>(re, im, lane, trig, kbase, grad);
+        grad_chunk<T, NQ, HI, PAR, LADDER, Q + 1, QEND, C0, H>(re, im, lr, li, acc);
     }
 }
 
-// Re <K_q x | lambda> for true qubit Q with the registers in the ladder
-// frame (the pairs and signs of ry_reg_ladder); lanes 0..31 hold the sum.
-template <typename T, int NQ, bool HI, int Q>
-__device__ __forceinline__ double grad_reg_ladder(const T* re, const T* im, int lane) {
-    using Ly = Lay<NQ, HI>;
-    constexpr int R = Ly::R;
-    constexpr int j = Ly::reg(Q);
-    constexpr int jp = Q + 1 < NQ ? Ly::reg(Q + 1) : -1;
-    static_assert(j >= 0 && (Q + 1 == NQ || jp >= 0), "pair not in registers");
-    constexpr int mask = (1 << j) | (jp >= 0 ? (1 << jp) : 0);
-    constexpr int low = HI ? ((1 << (Q - 5)) - 1) : ((1 << Q) - 1);
-    T acc = 0;
+// Qubit RB-1 in layout LO, ladder frame: the stored partner of (lane, r) is
+// (lane ^ 1, r ^ 2^(RB-1)) and r is the |0> member iff it has even parity.
+template <typename T, int NQ, int C0, int H>
+__device__ __forceinline__ T grad_lane_chunk(const T* re, const T* im, const T* lr, const T* li, T a) {
+    constexpr int j = Lay<NQ, false>::RB - 1;
 #pragma unroll
-    for (int r0 = 0; r0 < R; ++r0) {
-        if (r0 & (1 << j)) continue;
-        const int r1 = r0 ^ mask;
-        const T l0r = from_upper(re[r0]), l0i = from_upper(im[r0]);
-        const T l1r = from_upper(re[r1]), l1i = from_upper(im[r1]);
-        // stored r0 is the true |0> member unless the qubits below Q have odd parity
-        const T v = (re[r0] * l1r + im[r0] * l1i) - (re[r1] * l0r + im[r1] * l0i);
-        acc += odd_bits(r0 & low) ? -v : v;
+    for (int h = 0; h < H; ++h) {
+        const int r = C0 + h, q = r ^ (1 << j);
+        if (odd_bits(r)) {
+            a = fmat(re[q], lane_xor1(lr[h]), a);
+            a = fmat(im[q], lane_xor1(li[h]), a);
+        } else {
+            a = fmat(-lane_xor1(re[q]), lr[h], a);
+            a = fmat(-lane_xor1(im[q]), li[h], a);
+        }
     }
-    if constexpr (HI) {
-        if (__popc((unsigned)(lane & 31)) & 1) acc = -acc;
-    }
-    return (lane & 32) ? 0.0 : (double)acc;
+    return a;
 }
 
-// For every qubit q in [Q, QEND) (register pairs in the ladder frame):
-// gradient of RY_q, then RY_q undone.
-template <typename T, int NQ, bool HI, int Q, int QEND>
-__device__ __forceinline__ void grad_undo_range_ladder(T* re, T* im, int lane, const T* trig, int kbase,
-                                                       double* __restrict__ grad) {
+template <typename T, int NQ, bool HI, int PAR, bool LADDER, int Q, int QEND>
+__device__ __forceinline__ void grad_store(const T* acc, int lane, double* gb) {
     if constexpr (Q < QEND) {
-        const double gq = wave_sum(grad_reg_ladder<T, NQ, HI, Q>(re, im, lane));
-        if (lane == 0) grad[kbase + Q] = gq;
-        ry_reg_ladder<T, NQ, HI, Q>(re, im, lane, -trig[2 * (kbase + Q)], -trig[2 * (kbase + Q) + 1]);
-        grad_undo_range_ladder<T, NQ, HI, Q + 1, QEND>(re, im, lane, trig, kbase, grad);
+        if constexpr (Lay<NQ, HI>::reg(Q) >= 0) {
+            using Pr = PairOf<NQ, HI, Q, PAR, LADDER>;
+            const T a = Pr::lane_neg(lane) ? -acc[Q] : acc[Q];
+            if (lane < 32) gb[Q * 33 + lane] = (double)a;
+        }
+        grad_store<T, NQ, HI, PAR, LADDER, Q + 1, QEND>(acc, lane, gb);
     }
 }
 
-// Gradient and undo of RY on true qubit RB-1 in layout LO, ladder frame:
-// the stored partner of (lane, r) is (lane ^ 1, r ^ 2^(RB-1)), and the
-// amplitude is the true |0> member iff r has even parity, so each true pair
-// is counted once, from its |0> member.
-template <typename T, int NQ>
-__device__ __forceinline__ void grad_undo_lane_ladder_lo(T* re, T* im, int lane, const T* trig, int k,
-                                                         double* __restrict__ grad) {
-    using Ly = Lay<NQ, false>;
-    constexpr int R = Ly::R, j = Ly::RB - 1;
-    T acc = 0;
+// Partial gradient sums of the register qubits [Q, QEND) of layout HI (and,
+// with LANEQ, of qubit RB-1 of layout LO in the ladder frame) into gb.
+template <typename T, int NQ, bool HI, int PAR, bool LADDER, bool LANEQ, int Q, int QEND>
+__device__ __forceinline__ void grad_range(const T* re, const T* im, int lane, double* gb) {
+    constexpr int R = Lay<NQ, HI>::R, CH = kGradChunks<T, R>, H = R / CH;
+    constexpr int QL = Lay<NQ, false>::RB - 1;
+    T acc[NQ];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        if (odd_bits(r)) continue;
-        const int rp = r ^ (1 << j);
-        const T x1r = lane_xor1(re[rp]), x1i = lane_xor1(im[rp]);
-        const T l0r = from_upper(re[r]), l0i = from_upper(im[r]);
-        const T l1r = from_upper(x1r), l1i = from_upper(x1i);
-        const T v = (re[r] * l1r + im[r] * l1i) - (x1r * l0r + x1i * l0i);
-        acc += v;
+    for (int q = 0; q < NQ; ++q) acc[q] = (T)0;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        T lr[H], li[H];
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            lr[h] = from_upper(re[c * H + h]);
+            li[h] = from_upper(im[c * H + h]);
+        }
+        if (c == 0) {
+            grad_chunk<T, NQ, HI, PAR, LADDER, Q, QEND, 0, H>(re, im, lr, li, acc);
+            if constexpr (LANEQ) acc[QL] = grad_lane_chunk<T, NQ, 0, H>(re, im, lr, li, acc[QL]);
+        } else {
+            grad_chunk<T, NQ, HI, PAR, LADDER, Q, QEND, (CH > 1 ? H : 0), H>(re, im, lr, li, acc);
+            if constexpr (LANEQ) acc[QL] = grad_lane_chunk<T, NQ, (CH > 1 ? H : 0), H>(re, im, lr, li, acc[QL]);
+        }
     }
-    const double gq = wave_sum((lane & 32) ? 0.0 : (double)acc);
-    if (lane == 0) grad[k] = gq;
-    ry_lane_ladder_lo<T, NQ>(re, im, -trig[2 * k], -trig[2 * k + 1]);
+    grad_store<T, NQ, HI, PAR, LADDER, Q, QEND>(acc, lane, gb);
+    if constexpr (LANEQ) {
+        if (lane < 32) gb[QL * 33 + lane] = (double)acc[QL];
+    }
+}
+
+// Gradients of the register qubits [Q, QEND), then their RYs undone (CZ form).
+template <typename T, int NQ, bool HI, int PAR, int Q, int QEND>
+__device__ __forceinline__ void grad_undo_range(T* re, T* im, int lane, const T* trig, int kbase, double* gb) {
+    grad_range<T, NQ, HI, PAR, false, false, Q, QEND>(re, im, lane, gb);
+    ry_range<T, NQ, HI, PAR, Q, QEND>(re, im, lane, trig, kbase, (T)-1);
+}
+
+template <typename T, int NQ, bool HI, int Q, int QEND>
+__device__ __forceinline__ void undo_range_ladder(T* re, T* im, int lane, const T* trig, int kbase) {
+    if constexpr (Q < QEND) {
+        ry_reg_ladder<T, NQ, HI, Q>(re, im, lane, -trig[2 * (kbase + Q)], -trig[2 * (kbase + Q) + 1]);
+        undo_range_ladder<T, NQ, HI, Q + 1, QEND>(re, im, lane, trig, kbase);
+    }
+}
+
+// Ladder frame: gradients of qubits [Q, QEND) (and of qubit RB-1 across
+// lane bit 0 with LANEQ, layout LO), then their RYs undone.
+template <typename T, int NQ, bool HI, int Q, int QEND, bool LANEQ = false>
+__device__ __forceinline__ void grad_undo_range_ladder(T* re, T* im, int lane, const T* trig, int kbase,
+                                                       double* gb) {
+    grad_range<T, NQ, HI, 0, true, LANEQ, Q, QEND>(re, im, lane, gb);
+    if constexpr (LANEQ) {
+        constexpr int k = Lay<NQ, false>::RB - 1;
+        ry_lane_ladder_lo<T, NQ>(re, im, -trig[2 * (kbase + k)], -trig[2 * (kbase + k) + 1]);
+    }
+    undo_range_ladder<T, NQ, HI, Q, QEND>(re, im, lane, trig, kbase);
+}
+
+// Sum of the 32 partials of each qubit of the layer into g[0..NQ).
+template <int NQ>
+__device__ __forceinline__ void flush_grad(const double* gb, double* __restrict__ g, int lane) {
+    __syncthreads();
+    if (lane < NQ) {
+        const double* p = gb + lane * 33;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+        for (int i = 0; i < 32; i += 4) {
+            s0 += p[i];
+            s1 += p[i + 1];
+            s2 += p[i + 2];
+            s3 += p[i + 3];
+        }
+        g[lane] = (s0 + s1) + (s2 + s3);
+    }
+    __syncthreads();
 }
 
 // Layout swap into the ladder frame, the inverse of relayout_ladder: the
@@ -328,6 +397,7 @@ __host__ __device__ constexpr size_t wave_adjoint_lds(int layers, int L) {
     constexpr int regions = ENT == DVQ_ENT_CZ_LADDER ? 3 : 4;    // x, y/lambda, v (+ x in the ladder frame)
     return (size_t)(2 * N + (2 * N) / 32) * sizeof(cplx<T>)      // scratch for layout swaps
            + regions * (size_t)(N + N / 32) * sizeof(cplx<T>)
+           + (size_t)NQ * 33 * sizeof(double)                    // gradient partials
            + (size_t)L * (sizeof(dvq_pauli) + sizeof(dvq_c128))  // strings, coeffs
            + (size_t)2 * NQ * layers * sizeof(T);                // rotation table
 }
@@ -348,7 +418,8 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
     cplx<T>* RV = RY + N1;
     constexpr bool CNOT = ENT == DVQ_ENT_CNOT_LADDER;
     cplx<T>* RXF = RV + N1;  // x in the ladder frame (CNOT ladder only)
-    dvq_pauli* sp = reinterpret_cast<dvq_pauli*>(CNOT ? RXF + N1 : RV + N1);
+    double* gb = reinterpret_cast<double*>(CNOT ? RXF + N1 : RV + N1);  // gradient partials [NQ][33]
+    dvq_pauli* sp = reinterpret_cast<dvq_pauli*>(gb + NQ * 33);
     dvq_c128* cp = reinterpret_cast<dvq_c128*>(sp + L);
     T* trig = reinterpret_cast<T*>(cp + L);
     const int lane = threadIdx.x;
@@ -483,22 +554,24 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
             if (l & 1) {
                 // odd layer (forward: HI qubits in the frame, swap to LO,
                 // LO qubits 0..4): starts in LO, true state of its RYs
-                grad_undo_range<T, NQ, false, 0, 0, 5>(re, im, lane, trig, kb, g);
+                grad_undo_range<T, NQ, false, 0, 0, 5>(re, im, lane, trig, kb, gb);
                 relayout_to_ladder<T, NQ, false>(re, im, S, lane);
-                grad_undo_range_ladder<T, NQ, true, 5, NQ>(re, im, lane, trig, kb, g);
+                grad_undo_range_ladder<T, NQ, true, 5, NQ>(re, im, lane, trig, kb, gb);
             } else {
                 // even layer >= 2 (forward: LO qubits 0..RB-1 in the frame,
                 // swap to HI, HI qubits 5..NQ-1): starts in HI
-                grad_undo_range<T, NQ, true, 0, 5, NQ>(re, im, lane, trig, kb, g);
+                grad_undo_range<T, NQ, true, 0, 5, NQ>(re, im, lane, trig, kb, gb);
                 relayout_to_ladder<T, NQ, true>(re, im, S, lane);
-                if constexpr (RB - 1 < 5) grad_undo_lane_ladder_lo<T, NQ>(re, im, lane, trig, kb + RB - 1, g);
-                grad_undo_range_ladder<T, NQ, false, 0, RB - 1>(re, im, lane, trig, kb, g);
+                // qubit RB-1 across lane bit 0 when it is below 5 (else in HI above)
+                grad_undo_range_ladder<T, NQ, false, 0, RB - 1, (RB - 1 < 5)>(re, im, lane, trig, kb, gb);
             }
+            flush_grad<NQ>(gb, g + kb, lane);
         }
         // layer 0 (forward: LO qubits, plain swap, HI qubits RB..NQ-1): starts in HI
-        grad_undo_range<T, NQ, true, 0, RB, NQ>(re, im, lane, trig, 0, g);
+        grad_undo_range<T, NQ, true, 0, RB, NQ>(re, im, lane, trig, 0, gb);
         relayout<T, NQ, true>(re, im, S, lane);
-        grad_undo_range<T, NQ, false, 0, 0, NQ>(re, im, lane, trig, 0, g);
+        grad_undo_range<T, NQ, false, 0, 0, NQ>(re, im, lane, trig, 0, gb);
+        flush_grad<NQ>(gb, g, lane);
         if (lane == 0) Cout[row] = cost;
         return;
     }
@@ -506,22 +579,25 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
     if (pf) {
         // last layer even-indexed: ended in HI with p = 1 after its ladder
         load_halves<T, NQ, true>(re, im, RX, RY, lane, 1);
-        grad_undo_range<T, NQ, true, 0, Lay<NQ, false>::RB, NQ>(re, im, lane, trig, l * NQ, g);
+        grad_undo_range<T, NQ, true, 0, Lay<NQ, false>::RB, NQ>(re, im, lane, trig, l * NQ, gb);
         relayout<T, NQ, true>(re, im, S, lane);
-        grad_undo_range<T, NQ, false, 0, 0, NQ>(re, im, lane, trig, l * NQ, g);
+        grad_undo_range<T, NQ, false, 0, 0, NQ>(re, im, lane, trig, l * NQ, gb);
+        flush_grad<NQ>(gb, g + l * NQ, lane);
         --l;
     } else {
         load_halves<T, NQ, false>(re, im, RX, RY, lane, 0);
     }
     for (; l >= 1; l -= 2) {
         // odd layer l (p = 1 during its RYs): LO qubits 0..4, swap, HI qubits
-        grad_undo_range<T, NQ, false, 1, 0, 5>(re, im, lane, trig, l * NQ, g);
+        grad_undo_range<T, NQ, false, 1, 0, 5>(re, im, lane, trig, l * NQ, gb);
         relayout<T, NQ, false>(re, im, S, lane);
-        grad_undo_range<T, NQ, true, 1, 0, NQ>(re, im, lane, trig, l * NQ, g);
+        grad_undo_range<T, NQ, true, 1, 0, NQ>(re, im, lane, trig, l * NQ, gb);
+        flush_grad<NQ>(gb, g + l * NQ, lane);
         // even layer l - 1 (p = 0): HI qubits RB..NQ-1, swap, LO qubits
-        grad_undo_range<T, NQ, true, 0, Lay<NQ, false>::RB, NQ>(re, im, lane, trig, (l - 1) * NQ, g);
+        grad_undo_range<T, NQ, true, 0, Lay<NQ, false>::RB, NQ>(re, im, lane, trig, (l - 1) * NQ, gb);
         relayout<T, NQ, true>(re, im, S, lane);
-        grad_undo_range<T, NQ, false, 0, 0, NQ>(re, im, lane, trig, (l - 1) * NQ, g);
+        grad_undo_range<T, NQ, false, 0, 0, NQ>(re, im, lane, trig, (l - 1) * NQ, gb);
+        flush_grad<NQ>(gb, g + (l - 1) * NQ, lane);
     }
     if (lane == 0) Cout[row] = cost;
 }
