@@ -1,5 +1,8 @@
-// Adjoint gradient with the state in registers: one wavefront per parameter
-// row (n = 10, 11; CZ or CNOT ladder).  Same mathematics as k_adjoint (adjoint.hip):
+// Adjoint gradient with the state in registers: one workgroup of four
+// wavefronts per parameter row (n = 10, 11; CZ or CNOT ladder).  Every
+// wavefront holds the whole state and runs the register phases (the same
+// values, written to the same LDS slots); the Pauli sums are split between
+// them.  Same mathematics as k_adjoint (adjoint.hip):
 //   x = V(theta)|0>, y = A x (A = sum_l c_l P_l), Psi = <y|y>,
 //   local:  u = U_b^dag y, E = sum_k |u_k|^2 (n - 2|k|),
 //           v = dC/dE * U_b D u + dC/dPsi * y   (D = diag(n - 2|k|) = sum_j Z_j);
@@ -197,12 +200,13 @@ __device__ __forceinline__ void grad_undo_range_ladder(T* re, T* im, int lane, c
     undo_range_ladder<T, NQ, HI, Q, QEND>(re, im, lane, trig, kbase);
 }
 
-// Sum of the 32 partials of each qubit of the layer into g[0..NQ).
+// Sum of the 32 partials of each qubit of the layer into g[0..NQ), by the
+// first NQ threads of the block.
 template <int NQ>
-__device__ __forceinline__ void flush_grad(const double* gb, double* __restrict__ g, int lane) {
+__device__ __forceinline__ void flush_grad(const double* gb, double* __restrict__ g, int tid) {
     __syncthreads();
-    if (lane < NQ) {
-        const double* p = gb + lane * 33;
+    if (tid < NQ) {
+        const double* p = gb + tid * 33;
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
         for (int i = 0; i < 32; i += 4) {
@@ -211,7 +215,7 @@ __device__ __forceinline__ void flush_grad(const double* gb, double* __restrict_
             s2 += p[i + 2];
             s3 += p[i + 3];
         }
-        g[lane] = (s0 + s1) + (s2 + s3);
+        g[tid] = (s0 + s1) + (s2 + s3);
     }
     __syncthreads();
 }
@@ -327,66 +331,78 @@ __device__ __forceinline__ void store_half0(const T* re, const T* im, cplx<T>* S
 
 // out[k] = sum_l w_l (P_l in)[k] over natural-order regions, w_l = c_l or
 // conj(c_l).  (P in)[k] = i^{|x&z|} (-1)^{|z&x|} (-1)^{|z&k|} in[k^x]; with
-// k = lane + 64 i the last sign splits into a per-lane and a per-i part, so
-// the coefficient carries everything but the per-i sign, and each string
-// issues 2^NQ/64 independent gathers.
+// k = lane + 64 i the last sign splits into a per-lane part, folded into the
+// coefficient once per string, and a per-i part that is uniform over the
+// wavefront; the gather address is a per-lane base plus 66 (i ^ (x >> 6)),
+// also uniform.  The W wavefronts of a row take disjoint blocks of i.
 // With FRAME, out[k] receives the sum at index pi(k) (the ladder frame):
 // sum index m is written to slot pi^-1(m).
-template <typename T, int NQ, bool FRAME = false>
+template <typename T, int NQ, int W, bool FRAME = false>
 __device__ __forceinline__ void wave_pauli_sum(cplx<T>* out, const cplx<T>* in, const dvq_pauli* sp,
-                                               const dvq_c128* cp, int L, bool conj_c, int lane) {
-    constexpr int KPL = (1 << NQ) / 64;
-    T ar[KPL], ai[KPL];
+                                               const dvq_c128* cp, int L, bool conj_c, int lane, int wave) {
+    constexpr int KPL = (1 << NQ) / 64, KW = KPL / W;
+    static_assert(KW * W == KPL, "blocks per wavefront");
+    const int i0 = wave * KW;
+    T ar[KW], ai[KW];
 #pragma unroll
-    for (int i = 0; i < KPL; ++i) ar[i] = ai[i] = (T)0;
+    for (int i = 0; i < KW; ++i) ar[i] = ai[i] = (T)0;
     for (int l = 0; l < L; ++l) {
-        const uint32_t x = sp[l].x, z = sp[l].z;
+        const uint32_t x = __builtin_amdgcn_readfirstlane(sp[l].x), z = __builtin_amdgcn_readfirstlane(sp[l].z);
         cplx<T> c = {(T)cp[l].re, conj_c ? -(T)cp[l].im : (T)cp[l].im};
         c = mul_ipow(c, (int)__popc(x & z) + 2 * parity(z & x) + 2 * parity(z & (uint32_t)lane));
-        const int xl = (int)(x & 63u), xh = (int)(x >> 6);
+        const int bl = lane ^ (int)(x & 63u);
+        const cplx<T>* src = in + (bl + (bl >> 5));
+        const int xh = (int)(x >> 6), zh = (int)(z >> 6);
 #pragma unroll
-        for (int i = 0; i < KPL; ++i) {
-            const int kk = ((lane ^ xl) | ((i ^ xh) << 6));
-            const cplx<T> v = in[pad_slot(kk)];
-            const bool neg = parity(z & (uint32_t)(64 * i));
+        for (int i = 0; i < KW; ++i) {
+            const int ii = i0 + i;
+            const cplx<T> v = src[66 * (ii ^ xh)];
+            const bool neg = parity((uint32_t)(zh & ii));
             const T cr = neg ? -c.re : c.re, ci = neg ? -c.im : c.im;
-            ar[i] += cr * v.re - ci * v.im;
-            ai[i] += cr * v.im + ci * v.re;
+            ar[i] = fmat(cr, v.re, fmat(-ci, v.im, ar[i]));
+            ai[i] = fmat(cr, v.im, fmat(ci, v.re, ai[i]));
         }
     }
     if constexpr (FRAME) {
         const int ul = ladder_unperm<NQ>(lane);
 #pragma unroll
-        for (int i = 0; i < KPL; ++i) out[pad_slot(ul ^ ladder_unperm<NQ>(64 * i))] = {ar[i], ai[i]};
+        for (int i = 0; i < KW; ++i) out[pad_slot(ul ^ ladder_unperm<NQ>(64 * (i0 + i)))] = {ar[i], ai[i]};
     } else {
 #pragma unroll
-        for (int i = 0; i < KPL; ++i) out[pad_slot(lane + 64 * i)] = {ar[i], ai[i]};
+        for (int i = 0; i < KW; ++i) out[pad_slot(lane + 64 * (i0 + i))] = {ar[i], ai[i]};
     }
     __syncthreads();
 }
 
 // Householder U_b (= U_b^dagger) applied to a natural-order region in place.
+// Every lane reads its amplitudes before the barrier and writes after it, so
+// wavefronts that run this redundantly write the same values and never read
+// an updated one.
 template <typename T, int NQ>
 __device__ __forceinline__ void wave_householder(cplx<T>* v, const double* __restrict__ b, int lane) {
-    constexpr int N = 1 << NQ;
+    constexpr int N = 1 << NQ, KPL = N / 64;
     const double s = (b[0] > 0.0) ? -1.0 : 1.0;
     double ww = 0.0, dr = 0.0, di = 0.0;
-    for (int k = lane; k < N; k += 64) {
+    cplx<T> a[KPL];
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+        const int k = lane + 64 * i;
         const double w = (k == 0 ? 1.0 : 0.0) - s * b[k];
-        const cplx<T> a = v[pad_slot(k)];
+        a[i] = v[pad_slot(k)];
         ww += w * w;
-        dr += w * (double)a.re;
-        di += w * (double)a.im;
+        dr += w * (double)a[i].re;
+        di += w * (double)a[i].im;
     }
     ww = wave_sum(ww);
     dr = wave_sum(dr);
     di = wave_sum(di);
     const double fr = 2.0 * dr / ww, fi = 2.0 * di / ww;
     __syncthreads();
-    for (int k = lane; k < N; k += 64) {
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+        const int k = lane + 64 * i;
         const double w = (k == 0 ? 1.0 : 0.0) - s * b[k];
-        const cplx<T> a = v[pad_slot(k)];
-        v[pad_slot(k)] = {(T)(s * ((double)a.re - w * fr)), (T)(s * ((double)a.im - w * fi))};
+        v[pad_slot(k)] = {(T)(s * ((double)a[i].re - w * fr)), (T)(s * ((double)a[i].im - w * fi))};
     }
     __syncthreads();
 }
@@ -402,8 +418,8 @@ __host__ __device__ constexpr size_t wave_adjoint_lds(int layers, int L) {
            + (size_t)2 * NQ * layers * sizeof(T);                // rotation table
 }
 
-template <typename T, int NQ, int ENT>
-__global__ void __launch_bounds__(64)
+template <typename T, int NQ, int ENT, int W>
+__global__ void __launch_bounds__(64 * W)
 k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __restrict__ coeffs,
                const dvq_pauli* __restrict__ strings, int L, int per_row_system, int bkind,
                const double* __restrict__ bvec, int kind, double* __restrict__ Cout,
@@ -422,11 +438,14 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
     dvq_pauli* sp = reinterpret_cast<dvq_pauli*>(gb + NQ * 33);
     dvq_c128* cp = reinterpret_cast<dvq_c128*>(sp + L);
     T* trig = reinterpret_cast<T*>(cp + L);
-    const int lane = threadIdx.x;
+    // W wavefronts per row: each runs the register phases redundantly (same
+    // values written to the same LDS slots, every hand-over fenced by a
+    // barrier) and takes 1/W of the Pauli sums; wavefront 0 writes the results.
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t row = blockIdx.x;
     const int P = NQ * layers;
     const int64_t sys = per_row_system ? row * L : 0;
-    for (int l = lane; l < L; l += 64) {
+    for (int l = threadIdx.x; l < L; l += 64 * W) {
         sp[l] = strings[sys + l];
         cp[l] = coeffs[sys + l];
     }
@@ -460,7 +479,7 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
     }
 
     // y = A x, Psi = <y|y>
-    wave_pauli_sum<T, NQ>(RY, RX, sp, cp, L, false, lane);
+    wave_pauli_sum<T, NQ, W>(RY, RX, sp, cp, L, false, lane, wave);
     double ps = 0.0;
     for (int k = lane; k < N; k += 64) {
         const cplx<T> a = RY[pad_slot(k)];
@@ -499,11 +518,20 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
             __syncthreads();
             wave_householder<T, NQ>(RV, bvec, lane);
             double es = 0.0;
-            for (int k = lane; k < N; k += 64) {
-                const cplx<T> a = RV[pad_slot(k)];
+            cplx<T> a[N / 64];
+#pragma unroll
+            for (int i = 0; i < N / 64; ++i) {
+                const int k = lane + 64 * i;
+                a[i] = RV[pad_slot(k)];
+                es += ((double)a[i].re * a[i].re + (double)a[i].im * a[i].im) *
+                      (double)(NQ - 2 * (int)__popc((unsigned)k));
+            }
+            __syncthreads();  // read by every wavefront before the update
+#pragma unroll
+            for (int i = 0; i < N / 64; ++i) {
+                const int k = lane + 64 * i;
                 const T d = (T)(NQ - 2 * (int)__popc((unsigned)k));
-                es += ((double)a.re * a.re + (double)a.im * a.im) * (double)d;
-                RV[pad_slot(k)] = {a.re * d, a.im * d};
+                RV[pad_slot(k)] = {a[i].re * d, a[i].im * d};
             }
             const double E = wave_sum(es);
             __syncthreads();
@@ -512,9 +540,15 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
             aPsi = 0.5 * E / (NQ * Psi * Psi);
             wave_householder<T, NQ>(RV, bvec, lane);
         }
-        for (int k = lane; k < N; k += 64) {
-            const cplx<T> w = RV[pad_slot(k)], y = RY[pad_slot(k)];
-            RV[pad_slot(k)] = {(T)(aE * w.re + aPsi * y.re), (T)(aE * w.im + aPsi * y.im)};
+        cplx<T> w[N / 64];
+#pragma unroll
+        for (int i = 0; i < N / 64; ++i) w[i] = RV[pad_slot(lane + 64 * i)];
+        __syncthreads();  // read by every wavefront before the update
+#pragma unroll
+        for (int i = 0; i < N / 64; ++i) {
+            const int k = lane + 64 * i;
+            const cplx<T> y = RY[pad_slot(k)];
+            RV[pad_slot(k)] = {(T)(aE * w[i].re + aPsi * y.re), (T)(aE * w[i].im + aPsi * y.im)};
         }
         __syncthreads();
     } else {
@@ -539,7 +573,7 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
         __syncthreads();
     }
     // lambda = A^dag v -> RY (in the ladder frame for the CNOT ladder)
-    wave_pauli_sum<T, NQ, CNOT>(RY, RV, sp, cp, L, true, lane);
+    wave_pauli_sum<T, NQ, W, CNOT>(RY, RV, sp, cp, L, true, lane, wave);
 
     // reverse sweep: x in lanes 0..31, lambda in lanes 32..63
     double* g = grad + row * P;
@@ -565,14 +599,14 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
                 // qubit RB-1 across lane bit 0 when it is below 5 (else in HI above)
                 grad_undo_range_ladder<T, NQ, false, 0, RB - 1, (RB - 1 < 5)>(re, im, lane, trig, kb, gb);
             }
-            flush_grad<NQ>(gb, g + kb, lane);
+            flush_grad<NQ>(gb, g + kb, threadIdx.x);
         }
         // layer 0 (forward: LO qubits, plain swap, HI qubits RB..NQ-1): starts in HI
         grad_undo_range<T, NQ, true, 0, RB, NQ>(re, im, lane, trig, 0, gb);
         relayout<T, NQ, true>(re, im, S, lane);
         grad_undo_range<T, NQ, false, 0, 0, NQ>(re, im, lane, trig, 0, gb);
-        flush_grad<NQ>(gb, g, lane);
-        if (lane == 0) Cout[row] = cost;
+        flush_grad<NQ>(gb, g, threadIdx.x);
+        if (threadIdx.x == 0) Cout[row] = cost;
         return;
     }
     int l = layers - 1;
@@ -582,7 +616,7 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
         grad_undo_range<T, NQ, true, 0, Lay<NQ, false>::RB, NQ>(re, im, lane, trig, l * NQ, gb);
         relayout<T, NQ, true>(re, im, S, lane);
         grad_undo_range<T, NQ, false, 0, 0, NQ>(re, im, lane, trig, l * NQ, gb);
-        flush_grad<NQ>(gb, g + l * NQ, lane);
+        flush_grad<NQ>(gb, g + l * NQ, threadIdx.x);
         --l;
     } else {
         load_halves<T, NQ, false>(re, im, RX, RY, lane, 0);
@@ -592,14 +626,34 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
         grad_undo_range<T, NQ, false, 1, 0, 5>(re, im, lane, trig, l * NQ, gb);
         relayout<T, NQ, false>(re, im, S, lane);
         grad_undo_range<T, NQ, true, 1, 0, NQ>(re, im, lane, trig, l * NQ, gb);
-        flush_grad<NQ>(gb, g + l * NQ, lane);
+        flush_grad<NQ>(gb, g + l * NQ, threadIdx.x);
         // even layer l - 1 (p = 0): HI qubits RB..NQ-1, swap, LO qubits
         grad_undo_range<T, NQ, true, 0, Lay<NQ, false>::RB, NQ>(re, im, lane, trig, (l - 1) * NQ, gb);
         relayout<T, NQ, true>(re, im, S, lane);
         grad_undo_range<T, NQ, false, 0, 0, NQ>(re, im, lane, trig, (l - 1) * NQ, gb);
-        flush_grad<NQ>(gb, g + (l - 1) * NQ, lane);
+        flush_grad<NQ>(gb, g + (l - 1) * NQ, threadIdx.x);
     }
-    if (lane == 0) Cout[row] = cost;
+    if (threadIdx.x == 0) Cout[row] = cost;
+}
+
+// Wavefronts per row.  Four (one per SIMD of the row's CU) beat one at
+// every batch size measured (1 to 4096 rows, n = 10, 8 layers, L = 64): the
+// Pauli sums split four ways, the register phases run alongside, and a
+// row's LDS holds a CU to two workgroups, so one wavefront per row would
+// leave two of the four SIMDs idle.
+constexpr int kRowWaves = 4;
+
+template <typename T, int NQ, int ENT, int W>
+static dvq_status launch_adjoint_wave_w(const dvq_ansatz* an, const double* theta, int B, const dvq_c128* coeffs,
+                                        const dvq_pauli* strings, int L, int per_row_system, int bkind,
+                                        const double* b, int kind, double* C, double* grad, hipStream_t s) {
+    const size_t lds = wave_adjoint_lds<T, NQ, ENT>(an->layers, L);
+    if (lds > kMaxLdsBytes) return DVQ_EUNSUPPORTED;
+    DVQ_TRY_HIP(allow_lds((const void*)k_adjoint_wave<T, NQ, ENT, W>, lds));
+    hipLaunchKernelGGL((k_adjoint_wave<T, NQ, ENT, W>), dim3(B), dim3(64 * W), lds, s, theta, an->layers, coeffs,
+                       strings, L, per_row_system, bkind, b, kind, C, grad);
+    DVQ_CHECK_LAUNCH("k_adjoint_wave");
+    return DVQ_OK;
 }
 
 template <typename T, int NQ, int ENT>
@@ -607,13 +661,8 @@ static dvq_status launch_adjoint_wave_ent(const dvq_ansatz* an, const double* th
                                           const dvq_c128* coeffs, const dvq_pauli* strings, int L,
                                           int per_row_system, int bkind, const double* b, int kind,
                                           double* C, double* grad, hipStream_t s) {
-    const size_t lds = wave_adjoint_lds<T, NQ, ENT>(an->layers, L);
-    if (lds > kMaxLdsBytes) return DVQ_EUNSUPPORTED;
-    DVQ_TRY_HIP(allow_lds((const void*)k_adjoint_wave<T, NQ, ENT>, lds));
-    hipLaunchKernelGGL((k_adjoint_wave<T, NQ, ENT>), dim3(B), dim3(64), lds, s, theta, an->layers, coeffs,
-                       strings, L, per_row_system, bkind, b, kind, C, grad);
-    DVQ_CHECK_LAUNCH("k_adjoint_wave");
-    return DVQ_OK;
+    return launch_adjoint_wave_w<T, NQ, ENT, kRowWaves>(an, theta, B, coeffs, strings, L, per_row_system, bkind,
+                                                        b, kind, C, grad, s);
 }
 
 template <typename T, int NQ>

@@ -246,3 +246,26 @@ def test_register_adjoint_cnot_bench_system(layers):
             C, g = api.vqls_grad_adjoint(an, _gpu(th), _gpu(c), _gpu(strings), kind, precision)
             assert abs(C.item() - C0) < tol_c, (kind, precision)
             assert np.max(np.abs(g[0].cpu().numpy() - g0)) < tol_g, (kind, precision)
+
+
+@pytest.mark.parametrize("ent,precision,b_kind", [("cz", "f64", "plus"), ("cnot", "f32", "vector"),
+                                                  ("cnot", "f64", "plus")])
+def test_register_adjoint_rows_independent_of_batch(ent, precision, b_kind):
+    """Each row runs on four wavefronts (Pauli sums split, register phases
+    redundant): a row's result has the same bits in a batch of 300 and of
+    256, and sampled rows match the exact shift rule."""
+    n, layers = 10, 4
+    A, At, c, xs, zs, strings = _system(n, 1.0, -0.4, top_L=24)
+    b = random_unit_vector(1 << n, seed=3) if b_kind == "vector" else None
+    th = theta_uniform(300 * n * layers, seed=21).reshape(300, -1)
+    an = api.AnsatzSpec(n, layers, ent)
+    bb = None if b is None else _gpu(b)
+    C1, g1 = api.vqls_grad_adjoint(an, _gpu(th), _gpu(c), _gpu(strings), "local", precision, b_kind, bb)
+    C4, g4 = api.vqls_grad_adjoint(an, _gpu(th[:256]), _gpu(c), _gpu(strings), "local", precision, b_kind, bb)
+    assert torch.equal(C1[:256], C4) and torch.equal(g1[:256], g4)
+    tol_c, tol_g = (1e-12, 1e-10) if precision == "f64" else (1e-6, 1e-5)
+    for r in (0, 255, 299):
+        parts = lambda t: oc.parts_theta_dense(t, At, n, layers, ent, "local", b_kind, b)
+        C0, g0 = oc.grad_parameter_shift(parts, th[r], n, "local")
+        assert abs(C1[r].item() - C0) < tol_c
+        assert np.max(np.abs(g1[r].cpu().numpy() - g0)) < tol_g
