@@ -57,8 +57,10 @@ __device__ __forceinline__ double from_upper(double x) {
 // chunk (R / CH registers at a time, so at most that many extra registers
 // of each component are live); each register r of a chunk then adds, for
 // every qubit, lambda at r times x at its pair partner, negated when r is
-// the pair's |0> member, with the pair's frame sign.  Each lane keeps one
-// partial sum per qubit, written to LDS (gb[q * 33 + lane], lanes 0..31);
+// the pair's |0> member, with the pair's frame sign.  The W wavefronts of a
+// row hold the same registers and take every W-th qubit each.  Each lane
+// keeps one partial sum per qubit, written to LDS (gb[q * 33 + lane], lanes
+// 0..31);
 // flush_grad adds the 32 partials of each qubit once per layer, so no
 // cross-lane reduction sits in the sweep's dependency chain.
 
@@ -92,21 +94,23 @@ struct PairOf {
     }
 };
 
-template <typename T, int NQ, bool HI, int PAR, bool LADDER, int Q, int QEND, int C0, int H>
-__device__ __forceinline__ void grad_chunk(const T* re, const T* im, const T* lr, const T* li, T* acc) {
+template <typename T, int NQ, bool HI, int PAR, bool LADDER, int W, int Q, int QEND, int C0, int H>
+__device__ __forceinline__ void grad_chunk(const T* re, const T* im, const T* lr, const T* li, T* acc, int wave) {
     if constexpr (Q < QEND) {
         if constexpr (Lay<NQ, HI>::reg(Q) >= 0) {
-            using Pr = PairOf<NQ, HI, Q, PAR, LADDER>;
-            T a = acc[Q];
+            if (Q % W == wave) {  // each wavefront takes every W-th qubit
+                using Pr = PairOf<NQ, HI, Q, PAR, LADDER>;
+                T a = acc[Q];
 #pragma unroll
-            for (int h = 0; h < H; ++h) {
-                const int r = C0 + h, p = Pr::partner(r);
-                a = fmat(Pr::plus(r) ? re[p] : -re[p], lr[h], a);
-                a = fmat(Pr::plus(r) ? im[p] : -im[p], li[h], a);
+                for (int h = 0; h < H; ++h) {
+                    const int r = C0 + h, p = Pr::partner(r);
+                    a = fmat(Pr::plus(r) ? re[p] : -re[p], lr[h], a);
+                    a = fmat(Pr::plus(r) ? im[p] : -im[p], li[h], a);
+                }
+                acc[Q] = a;
             }
-            acc[Q] = a;
         }
-        grad_chunk<T, NQ, HI, PAR, LADDER, Q + 1, QEND, C0, H>(re, im, lr, li, acc);
+        grad_chunk<T, NQ, HI, PAR, LADDER, W, Q + 1, QEND, C0, H>(re, im, lr, li, acc, wave);
     }
 }
 
@@ -129,22 +133,22 @@ __device__ __forceinline__ T grad_lane_chunk(const T* re, const T* im, const T* 
     return a;
 }
 
-template <typename T, int NQ, bool HI, int PAR, bool LADDER, int Q, int QEND>
-__device__ __forceinline__ void grad_store(const T* acc, int lane, double* gb) {
+template <typename T, int NQ, bool HI, int PAR, bool LADDER, int W, int Q, int QEND>
+__device__ __forceinline__ void grad_store(const T* acc, int lane, double* gb, int wave) {
     if constexpr (Q < QEND) {
         if constexpr (Lay<NQ, HI>::reg(Q) >= 0) {
             using Pr = PairOf<NQ, HI, Q, PAR, LADDER>;
             const T a = Pr::lane_neg(lane) ? -acc[Q] : acc[Q];
-            if (lane < 32) gb[Q * 33 + lane] = (double)a;
+            if (lane < 32 && Q % W == wave) gb[Q * 33 + lane] = (double)a;
         }
-        grad_store<T, NQ, HI, PAR, LADDER, Q + 1, QEND>(acc, lane, gb);
+        grad_store<T, NQ, HI, PAR, LADDER, W, Q + 1, QEND>(acc, lane, gb, wave);
     }
 }
 
 // Partial gradient sums of the register qubits [Q, QEND) of layout HI (and,
 // with LANEQ, of qubit RB-1 of layout LO in the ladder frame) into gb.
-template <typename T, int NQ, bool HI, int PAR, bool LADDER, bool LANEQ, int Q, int QEND>
-__device__ __forceinline__ void grad_range(const T* re, const T* im, int lane, double* gb) {
+template <typename T, int NQ, bool HI, int PAR, bool LADDER, bool LANEQ, int W, int Q, int QEND>
+__device__ __forceinline__ void grad_range(const T* re, const T* im, int lane, double* gb, int wave) {
     constexpr int R = Lay<NQ, HI>::R, CH = kGradChunks<T, R>, H = R / CH;
     constexpr int QL = Lay<NQ, false>::RB - 1;
     T acc[NQ];
@@ -159,23 +163,26 @@ __device__ __forceinline__ void grad_range(const T* re, const T* im, int lane, d
             li[h] = from_upper(im[c * H + h]);
         }
         if (c == 0) {
-            grad_chunk<T, NQ, HI, PAR, LADDER, Q, QEND, 0, H>(re, im, lr, li, acc);
-            if constexpr (LANEQ) acc[QL] = grad_lane_chunk<T, NQ, 0, H>(re, im, lr, li, acc[QL]);
+            grad_chunk<T, NQ, HI, PAR, LADDER, W, Q, QEND, 0, H>(re, im, lr, li, acc, wave);
+            if constexpr (LANEQ)
+                if (QL % W == wave) acc[QL] = grad_lane_chunk<T, NQ, 0, H>(re, im, lr, li, acc[QL]);
         } else {
-            grad_chunk<T, NQ, HI, PAR, LADDER, Q, QEND, (CH > 1 ? H : 0), H>(re, im, lr, li, acc);
-            if constexpr (LANEQ) acc[QL] = grad_lane_chunk<T, NQ, (CH > 1 ? H : 0), H>(re, im, lr, li, acc[QL]);
+            grad_chunk<T, NQ, HI, PAR, LADDER, W, Q, QEND, (CH > 1 ? H : 0), H>(re, im, lr, li, acc, wave);
+            if constexpr (LANEQ)
+                if (QL % W == wave) acc[QL] = grad_lane_chunk<T, NQ, (CH > 1 ? H : 0), H>(re, im, lr, li, acc[QL]);
         }
     }
-    grad_store<T, NQ, HI, PAR, LADDER, Q, QEND>(acc, lane, gb);
+    grad_store<T, NQ, HI, PAR, LADDER, W, Q, QEND>(acc, lane, gb, wave);
     if constexpr (LANEQ) {
-        if (lane < 32) gb[QL * 33 + lane] = (double)acc[QL];
+        if (lane < 32 && QL % W == wave) gb[QL * 33 + lane] = (double)acc[QL];
     }
 }
 
 // Gradients of the register qubits [Q, QEND), then their RYs undone (CZ form).
-template <typename T, int NQ, bool HI, int PAR, int Q, int QEND>
-__device__ __forceinline__ void grad_undo_range(T* re, T* im, int lane, const T* trig, int kbase, double* gb) {
-    grad_range<T, NQ, HI, PAR, false, false, Q, QEND>(re, im, lane, gb);
+template <typename T, int NQ, bool HI, int PAR, int W, int Q, int QEND>
+__device__ __forceinline__ void grad_undo_range(T* re, T* im, int lane, const T* trig, int kbase, double* gb,
+                                                int wave) {
+    grad_range<T, NQ, HI, PAR, false, false, W, Q, QEND>(re, im, lane, gb, wave);
     ry_range<T, NQ, HI, PAR, Q, QEND>(re, im, lane, trig, kbase, (T)-1);
 }
 
@@ -189,10 +196,10 @@ __device__ __forceinline__ void undo_range_ladder(T* re, T* im, int lane, const 
 
 // Ladder frame: gradients of qubits [Q, QEND) (and of qubit RB-1 across
 // lane bit 0 with LANEQ, layout LO), then their RYs undone.
-template <typename T, int NQ, bool HI, int Q, int QEND, bool LANEQ = false>
+template <typename T, int NQ, bool HI, int W, int Q, int QEND, bool LANEQ = false>
 __device__ __forceinline__ void grad_undo_range_ladder(T* re, T* im, int lane, const T* trig, int kbase,
-                                                       double* gb) {
-    grad_range<T, NQ, HI, 0, true, LANEQ, Q, QEND>(re, im, lane, gb);
+                                                       double* gb, int wave) {
+    grad_range<T, NQ, HI, 0, true, LANEQ, W, Q, QEND>(re, im, lane, gb, wave);
     if constexpr (LANEQ) {
         constexpr int k = Lay<NQ, false>::RB - 1;
         ry_lane_ladder_lo<T, NQ>(re, im, -trig[2 * (kbase + k)], -trig[2 * (kbase + k) + 1]);
@@ -588,23 +595,23 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
             if (l & 1) {
                 // odd layer (forward: HI qubits in the frame, swap to LO,
                 // LO qubits 0..4): starts in LO, true state of its RYs
-                grad_undo_range<T, NQ, false, 0, 0, 5>(re, im, lane, trig, kb, gb);
+                grad_undo_range<T, NQ, false, 0, W, 0, 5>(re, im, lane, trig, kb, gb, wave);
                 relayout_to_ladder<T, NQ, false>(re, im, S, lane);
-                grad_undo_range_ladder<T, NQ, true, 5, NQ>(re, im, lane, trig, kb, gb);
+                grad_undo_range_ladder<T, NQ, true, W, 5, NQ>(re, im, lane, trig, kb, gb, wave);
             } else {
                 // even layer >= 2 (forward: LO qubits 0..RB-1 in the frame,
                 // swap to HI, HI qubits 5..NQ-1): starts in HI
-                grad_undo_range<T, NQ, true, 0, 5, NQ>(re, im, lane, trig, kb, gb);
+                grad_undo_range<T, NQ, true, 0, W, 5, NQ>(re, im, lane, trig, kb, gb, wave);
                 relayout_to_ladder<T, NQ, true>(re, im, S, lane);
                 // qubit RB-1 across lane bit 0 when it is below 5 (else in HI above)
-                grad_undo_range_ladder<T, NQ, false, 0, RB - 1, (RB - 1 < 5)>(re, im, lane, trig, kb, gb);
+                grad_undo_range_ladder<T, NQ, false, W, 0, RB - 1, (RB - 1 < 5)>(re, im, lane, trig, kb, gb, wave);
             }
             flush_grad<NQ>(gb, g + kb, threadIdx.x);
         }
         // layer 0 (forward: LO qubits, plain swap, HI qubits RB..NQ-1): starts in HI
-        grad_undo_range<T, NQ, true, 0, RB, NQ>(re, im, lane, trig, 0, gb);
+        grad_undo_range<T, NQ, true, 0, W, RB, NQ>(re, im, lane, trig, 0, gb, wave);
         relayout<T, NQ, true>(re, im, S, lane);
-        grad_undo_range<T, NQ, false, 0, 0, NQ>(re, im, lane, trig, 0, gb);
+        grad_undo_range<T, NQ, false, 0, W, 0, NQ>(re, im, lane, trig, 0, gb, wave);
         flush_grad<NQ>(gb, g, threadIdx.x);
         if (threadIdx.x == 0) Cout[row] = cost;
         return;
@@ -613,9 +620,9 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
     if (pf) {
         // last layer even-indexed: ended in HI with p = 1 after its ladder
         load_halves<T, NQ, true>(re, im, RX, RY, lane, 1);
-        grad_undo_range<T, NQ, true, 0, Lay<NQ, false>::RB, NQ>(re, im, lane, trig, l * NQ, gb);
+        grad_undo_range<T, NQ, true, 0, W, Lay<NQ, false>::RB, NQ>(re, im, lane, trig, l * NQ, gb, wave);
         relayout<T, NQ, true>(re, im, S, lane);
-        grad_undo_range<T, NQ, false, 0, 0, NQ>(re, im, lane, trig, l * NQ, gb);
+        grad_undo_range<T, NQ, false, 0, W, 0, NQ>(re, im, lane, trig, l * NQ, gb, wave);
         flush_grad<NQ>(gb, g + l * NQ, threadIdx.x);
         --l;
     } else {
@@ -623,14 +630,14 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
     }
     for (; l >= 1; l -= 2) {
         // odd layer l (p = 1 during its RYs): LO qubits 0..4, swap, HI qubits
-        grad_undo_range<T, NQ, false, 1, 0, 5>(re, im, lane, trig, l * NQ, gb);
+        grad_undo_range<T, NQ, false, 1, W, 0, 5>(re, im, lane, trig, l * NQ, gb, wave);
         relayout<T, NQ, false>(re, im, S, lane);
-        grad_undo_range<T, NQ, true, 1, 0, NQ>(re, im, lane, trig, l * NQ, gb);
+        grad_undo_range<T, NQ, true, 1, W, 0, NQ>(re, im, lane, trig, l * NQ, gb, wave);
         flush_grad<NQ>(gb, g + l * NQ, threadIdx.x);
         // even layer l - 1 (p = 0): HI qubits RB..NQ-1, swap, LO qubits
-        grad_undo_range<T, NQ, true, 0, Lay<NQ, false>::RB, NQ>(re, im, lane, trig, (l - 1) * NQ, gb);
+        grad_undo_range<T, NQ, true, 0, W, Lay<NQ, false>::RB, NQ>(re, im, lane, trig, (l - 1) * NQ, gb, wave);
         relayout<T, NQ, true>(re, im, S, lane);
-        grad_undo_range<T, NQ, false, 0, 0, NQ>(re, im, lane, trig, (l - 1) * NQ, gb);
+        grad_undo_range<T, NQ, false, 0, W, 0, NQ>(re, im, lane, trig, (l - 1) * NQ, gb, wave);
         flush_grad<NQ>(gb, g + (l - 1) * NQ, threadIdx.x);
     }
     if (threadIdx.x == 0) Cout[row] = cost;
