@@ -57,12 +57,12 @@ CSRC = os.path.join(ROOT, "paper_2604_14435_amd", "csrc")
 MEASURED_TRAFFIC = {
     "k_terms_fast<float,10,cz,plus>": {
         "sources": ["circuits_fast.hip", "wave_state.h", "circuits.h", "common.h"],
-        "sources_sha256": "60c7eba2c9d37357", "fetch_kib": 200.3, "write_kib": 10897.4},
+        "sources_sha256": "7982a1a79fd181a3", "fetch_kib": 198.0, "write_kib": 704.0},
     "k_fwht_fused<6,2> (n=12 dense)": {
         "sources": ["decompose.hip", "common.h"],
-        "sources_sha256": "6f82fc5f8a9e75fe", "fetch_kib": 66123.9, "write_kib": 262227.8},
+        "sources_sha256": "6f82fc5f8a9e75fe", "fetch_kib": 66021.4, "write_kib": 262233.0},
 }
-FETCH_SCALE, WRITE_SCALE = 262144.0 / 131092.6, 1.0
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131088.8, 1.0
 
 
 def sources_sha256(names) -> str:
@@ -861,6 +861,34 @@ def heleshaw_run(api, dev, reps=3, iters=200):
             "condition_number": float(np.linalg.cond(A))}
 
 
+def adjoint_rows(api, dev, coeffs, strings, reps=50):
+    """Register adjoint (one cost + gradient evaluation per row, four
+    wavefronts per row) on the n=10 L=64 system: one row, as each L-BFGS
+    evaluation runs it, for both ladders and depths, and a batch of 4096 rows
+    (HIP-event averages)."""
+    import torch
+    from workloads import theta_uniform
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {}
+    for ent, layers, prec, B in (("cz", 4, "f32", 1), ("cnot", 4, "f32", 1), ("cnot", 8, "f32", 1),
+                                 ("cnot", 8, "f64", 1), ("cnot", 8, "f32", 4096), ("cnot", 8, "f64", 4096)):
+        an = api.AnsatzSpec(N_QUBITS, layers, ent)
+        th = torch.from_numpy(theta_uniform(an.P * B, seed=0).reshape(B, -1)).to(dev)
+        C, g = api.vqls_grad_adjoint(an, th, coeffs, strings, "local", prec)
+        torch.cuda.synchronize()
+        r = reps if B == 1 else 5
+        e0.record()
+        for _ in range(r):
+            api.vqls_grad_adjoint(an, th, coeffs, strings, "local", prec, out=(C, g))
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / r
+        key = f"{ent}_{layers}layers_{prec}" + ("" if B == 1 else f"_{B}rows")
+        res[key] = {"rows": B, "ms": round(ms, 4), "us_per_row": round(ms * 1e3 / B, 3)}
+    return res
+
+
 def adjoint_workload(api, dev, reps=5):
     """n = 10, tridiag(-0.45, 1, -0.45), tau = 0.005 -> L = 128, 6 layers
     RY + CZ ladder (60 angles), local cost, b = |+>, theta from seed 0: one
@@ -1188,8 +1216,8 @@ def main() -> int:
     e1.record()
     torch.cuda.synchronize()
     shared_ms = e0.elapsed_time(e1) / args.steps
-    # the complex64 adjoint alone (one wavefront; it runs beside the circuits
-    # on the second stream of every step)
+    # the complex64 adjoint alone (one row; it runs beside the circuits on
+    # the second stream of every step)
     Cadj = torch.empty(1, dtype=torch.float64, device=dev)
     gadj = torch.empty((1, P), dtype=torch.float64, device=dev)
     th1 = theta0.view(1, -1)
@@ -1305,6 +1333,8 @@ def main() -> int:
     }
     progress("precision comparison done")
     out["pruning_sweep"] = pruning_sweep(api, dev)
+    out["adjoint_rows_L64"] = adjoint_rows(api, dev, coeffs, strings)
+    progress("register adjoint rows timed")
     out["adjoint_L128"] = adjoint_workload(api, dev)
     progress("L=128 adjoint workload done")
     out["multi_rhs"] = multi_rhs(api, dev, coeffs, strings)

@@ -464,6 +464,18 @@ constexpr int fast_waves() {
     return planar_lds<T, ENT, BVEC>() ? 4 : 1;
 }
 
+// Workgroup b of a launch runs on XCD b mod 8: the dispatcher deals
+// workgroups to the eight XCDs in turn, and each XCD has its own L2.  Mapping
+// each XCD's workgroups to one contiguous range of circuits keeps neighbouring
+// 8-byte results (the two parts of a term, then the next term) in one L2, so
+// they leave it as whole 32-byte sectors instead of one partial sector each.
+// A bijection of [0, G) for any G.
+__device__ __forceinline__ int64_t xcd_contiguous(int64_t b, int64_t G) {
+    constexpr int64_t kXcds = 8;
+    const int64_t q = G / kXcds, r = G % kXcds, x = b % kXcds;
+    return x * q + (x < r ? x : r) + b / kXcds;
+}
+
 template <typename T, int NQ, int ENT, bool BVEC>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(fast_waves<T, NQ, ENT, BVEC>()))) k_terms_fast(TermsArgs g) {
     constexpr int N = 1 << NQ;
@@ -472,7 +484,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(fast_wa
     const int lane = threadIdx.x;
     const int P = NQ * g.layers;
 
-    const int64_t gid = (int64_t)blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
+    const int64_t gid = xcd_contiguous((int64_t)blockIdx.x + (int64_t)blockIdx.y * gridDim.x,
+                                       (int64_t)gridDim.x * gridDim.y);
     if (gid >= g.total) return;
     const int64_t row = gid / g.per_row;
     const Term t = decode_term(g.c0 + gid - row * g.per_row, g.L, NQ, g.kind);
