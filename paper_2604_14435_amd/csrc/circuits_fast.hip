@@ -211,7 +211,10 @@ __device__ __forceinline__ void measure_suffix_pair(const cplx<T>* S, SignedPerm
 // pending ladder sign or frame).  After the real parts each lane keeps its
 // ancilla = 0 amplitudes' real parts and the real parts of the permuted
 // ancilla = 1 amplitudes; with the imaginary parts it completes each pair
-// and applies the same S^dagger / H / <Z_anc> as measure_suffix.
+// and applies the same S^dagger / H / <Z_anc> as measure_suffix.  The
+// registers are as prefix_registers left them, except that with the CNOT
+// ladder at odd depth the caller has swapped them from HI (ladder frame) to
+// LO (true frame) first.
 template <typename T, int NQ, int ENT>
 __device__ __forceinline__ void store_final_plane(const T* x, T* P, int layers, int lane) {
     if constexpr (ENT == DVQ_ENT_CZ_LADDER) {
@@ -230,8 +233,6 @@ __device__ __forceinline__ void store_final_plane(const T* x, T* P, int layers, 
 template <typename T, int NQ, int ENT>
 __device__ __forceinline__ T measure_planar(T* re, T* im, T* P, SignedPerm sp, int imag, int layers, int lane) {
     constexpr int N = 1 << NQ, KPL = N / 64;
-    if constexpr (ENT != DVQ_ENT_CZ_LADDER)
-        if (layers & 1) relayout_ladder<T, NQ, true>(re, im, P, lane);  // HI ladder frame -> LO true frame
     const SuffixLane sl = suffix_lane(sp, lane);
     // pad_slot(lane + 64 i) = a0 + 66 i: one base, the offsets are immediates
     const int a0 = lane + (lane >> 5);
@@ -353,25 +354,29 @@ template <typename T, int NQ, int ENT>
 __device__ __forceinline__ T measure_planar_bvec(T* re, T* im, T* P, dvq_pauli pl, dvq_pauli pm, int j,
                                                  const double* __restrict__ b, int imag, int layers, int lane) {
     constexpr int N = 1 << NQ, KPL = N / 64;
-    if constexpr (ENT != DVQ_ENT_CZ_LADDER)
-        if (layers & 1) relayout_ladder<T, NQ, true>(re, im, P, lane);  // HI ladder frame -> LO true frame
     const double sg = (b[0] > 0.0) ? -1.0 : 1.0;
     const int pwm = string_pow(pm);
+    // pad_slot(lane + 64 i) = a0 + 66 i and pad_slot(N + (k ^ X_m)) =
+    // pad_slot(N) + um + 66 (i ^ (X_m >> 6)): per-lane bases, immediate or
+    // wave-uniform offsets; the gather addresses are formed again after each
+    // barrier rather than held in registers across the plane stores.
+    const int a0 = lane + (lane >> 5);
+    const int bm = lane ^ (int)(pm.x & 63u), xhm = (int)(pm.x >> 6);
+    int um = N + (N >> 5) + bm + (bm >> 5);
     T a0r[KPL], a0i[KPL], ur[KPL], ui[KPL];
     store_final_plane<T, NQ, ENT>(re, P, layers, lane);
 #pragma unroll
     for (int i = 0; i < KPL; ++i) {
-        const int k = lane + 64 * i;
-        a0r[i] = P[pad_slot(k)];
-        ur[i] = P[pad_slot(N + (k ^ (int)pm.x))];
+        a0r[i] = P[a0 + 66 * i];
+        ur[i] = P[um + 66 * (i ^ xhm)];
     }
     __syncthreads();  // every lane has read the real parts
     store_final_plane<T, NQ, ENT>(im, P, layers, lane);
+    asm volatile("" : "+v"(um));
 #pragma unroll
     for (int i = 0; i < KPL; ++i) {
-        const int k = lane + 64 * i;
-        a0i[i] = P[pad_slot(k)];
-        ui[i] = P[pad_slot(N + (k ^ (int)pm.x))];
+        a0i[i] = P[a0 + 66 * i];
+        ui[i] = P[um + 66 * (i ^ xhm)];
     }
     __syncthreads();  // every lane has read the imaginary parts
     T ar = 0, ai = 0, br = 0, bi = 0, ze = 0, om = 0;
@@ -415,53 +420,39 @@ __device__ __forceinline__ T measure_planar_bvec(T* re, T* im, T* P, dvq_pauli p
     sp.Z = pl.z;
     sp.pw = string_pow(pl);
     const SuffixLane sl = suffix_lane(sp, lane);
+    const int a1 = N + (N >> 5) + a0;  // pad_slot(N + lane + 64 i) = a1 + 66 i
     T gr[KPL];
 #pragma unroll
-    for (int i = 0; i < KPL; ++i) P[pad_slot(N + lane + 64 * i)] = ur[i];
+    for (int i = 0; i < KPL; ++i) P[a1 + 66 * i] = ur[i];
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < KPL; ++i) gr[i] = P[suffix_slot(sl, N, i)];
     __syncthreads();  // every lane has read the real parts of A_l v
 #pragma unroll
-    for (int i = 0; i < KPL; ++i) P[pad_slot(N + lane + 64 * i)] = ui[i];
+    for (int i = 0; i < KPL; ++i) P[a1 + 66 * i] = ui[i];
     __syncthreads();
+    SuffixLane sl2 = sl;
+    asm volatile("" : "+v"(sl2.base));
     const PhaseSplit<T> ph(sl, imag);
     T s1 = 0, s2 = 0;
 #pragma unroll
     for (int i = 0; i < KPL; ++i) {
         const T sgn = (__popc((unsigned)(i & sl.zh)) & 1) ? (T)-1 : (T)1;
-        z_sums(a0r[i], a0i[i], gr[i], P[suffix_slot(sl, N, i)], sgn, s1, s2);
+        z_sums(a0r[i], a0i[i], gr[i], P[suffix_slot(sl2, N, i)], sgn, s1, s2);
     }
     return (T)2 * wave_sum(fmat(ph.c, s1, ph.d * s2));
 }
 
-// Literal form: one wavefront simulates one circuit, every gate.
-// (No occupancy bound in the launch bounds: bounding the float32 kernel to
-// 128 VGPRs for four wavefronts per SIMD spilled to scratch and measured
-// 4 % slower.)
-// The literal kernel keeps a planar LDS image: half the LDS per wavefront
-// of an interleaved one, so the register count sets the occupancy.  n = 10,
-// b = |+>: float32 four wavefronts per SIMD (127 VGPRs with the CZ ladder,
-// 125 with CNOT; 2.25 with the 17 KB interleaved image); float64 two (one
-// with the 33 KB interleaved image).  General b: three in float32 with the
-// CZ ladder (140 VGPRs); the CNOT ladder's general-b kernel would need 201
-// VGPRs planar and keeps the interleaved image (134 VGPRs, 2.25).
-template <typename T, int ENT, bool BVEC>
-__host__ __device__ constexpr bool planar_lds() {
-    return !(BVEC && ENT == DVQ_ENT_CNOT_LADDER && sizeof(T) == 4);
-}
-
-// Minimum wavefronts per SIMD the compiler is asked to fit: five for the
-// float32 b = |+> kernels at NQ <= 10 (96 VGPRs with a 28-40 byte spill;
-// the LDS image then allows 18 wavefronts per CU instead of 16), four for
-// the float32 general-b kernel on the planar image (128 VGPRs, 36-byte
-// spill); no bound elsewhere (the interleaved image caps occupancy through
-// LDS, and larger states would spill heavily).
+// Literal form: one wavefront simulates one circuit, every gate, on the
+// planar LDS image (half the LDS of an interleaved one, so the register
+// count sets the occupancy).  Float32, n <= 10: five wavefronts per SIMD for
+// b = |+> (96 VGPRs; the 8.6 KB image then allows 18 per CU), four for a
+// general b (126 VGPRs), both ladders, no spill; larger states and float64
+// take no bound (a bound would spill heavily).
 template <typename T, int NQ, int ENT, bool BVEC>
 constexpr int fast_waves() {
     if (sizeof(T) != 4 || NQ > 10) return 1;
-    if (!BVEC) return 5;
-    return planar_lds<T, ENT, BVEC>() ? 4 : 1;
+    return BVEC ? 4 : 5;
 }
 
 // Workgroup b of a launch runs on XCD b mod 8: the dispatcher deals
@@ -490,34 +481,22 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(fast_wa
     const int64_t row = gid / g.per_row;
     const Term t = decode_term(g.c0 + gid - row * g.per_row, g.L, NQ, g.kind);
 
-    if constexpr (planar_lds<T, ENT, BVEC>()) {
-        T* Pl = reinterpret_cast<T*>(smem);
-        T* trig = Pl + NSLOT;
-        constexpr int R = Lay<NQ, false>::R;
-        T re[R], im[R];
-        prefix_registers<T, NQ, ENT>(g.theta + row * P, g.layers, Pl, trig, lane, re, im);
-        T z;
-        if (BVEC && t.type == kDelta) {
-            z = measure_planar_bvec<T, NQ, ENT>(re, im, Pl, g.strings[t.l], g.strings[t.m], t.j, g.b, t.part,
-                                                g.layers, lane);
-        } else {
-            const SignedPerm sp = suffix_perm(g.strings[t.l], g.strings[t.m], t.type, t.j);
-            z = measure_planar<T, NQ, ENT>(re, im, Pl, sp, t.part, g.layers, lane);
-        }
-        if (lane == 0) store_term(g, row, t, (double)z);
-        return;
-    }
-    cplx<T>* S = reinterpret_cast<cplx<T>*>(smem);
-    T* trig = reinterpret_cast<T*>(S + NSLOT);
-    simulate_prefix<T, NQ, ENT>(g.theta + row * P, g.layers, S, trig, lane);
+    T* Pl = reinterpret_cast<T*>(smem);
+    T* trig = Pl + NSLOT;
+    constexpr int R = Lay<NQ, false>::R;
+    T re[R], im[R];
+    prefix_registers<T, NQ, ENT>(g.theta + row * P, g.layers, Pl, trig, lane, re, im);
+    // the measurements start in layout LO (true frame for the CNOT ladder);
+    // once here rather than in each, so both share one register assignment
+    if constexpr (ENT != DVQ_ENT_CZ_LADDER)
+        if (g.layers & 1) relayout_ladder<T, NQ, true>(re, im, Pl, lane);  // HI ladder frame -> LO true frame
     T z;
     if (BVEC && t.type == kDelta) {
-        T zr, zi;
-        measure_suffix_bvec<T, NQ>(S, g.strings[t.l], g.strings[t.m], t.j, g.b, lane, zr, zi, N);
-        z = t.part ? zi : zr;
+        z = measure_planar_bvec<T, NQ, ENT>(re, im, Pl, g.strings[t.l], g.strings[t.m], t.j, g.b, t.part,
+                                            g.layers, lane);
     } else {
         const SignedPerm sp = suffix_perm(g.strings[t.l], g.strings[t.m], t.type, t.j);
-        z = measure_suffix<T, NQ>(S, sp, t.part, lane);
+        z = measure_planar<T, NQ, ENT>(re, im, Pl, sp, t.part, g.layers, lane);
     }
     if (lane == 0) store_term(g, row, t, (double)z);
 }
@@ -571,7 +550,7 @@ static size_t fast_lds_bytes(int layers, bool planar = false) {
 
 template <typename T, int NQ, int ENT, bool BVEC>
 static dvq_status launch_fast_ent(const TermsArgs& g, hipStream_t s) {
-    const size_t lds = fast_lds_bytes<T, NQ>(g.layers, planar_lds<T, ENT, BVEC>());
+    const size_t lds = fast_lds_bytes<T, NQ>(g.layers, true);
     DVQ_TRY_HIP(allow_lds((const void*)k_terms_fast<T, NQ, ENT, BVEC>, lds));
     hipLaunchKernelGGL((k_terms_fast<T, NQ, ENT, BVEC>), grid_for(g.total), dim3(64), lds, s, g);
     DVQ_CHECK_LAUNCH("k_terms_fast");
