@@ -55,10 +55,12 @@ namespace dvq {
 // The prefix in registers: |0> with H on the ancilla (1/sqrt(2) at g = 0
 // and g = 2^n, layout LO), then V(theta), swapping layouts through the LDS
 // image S (interleaved cplx<T>* or planar T*).  Ends as forward_layers /
-// forward_layers_ladder leave it.
+// forward_layers_ladder leave it.  The layout swaps address S with
+// `slot_lane`: the lane itself, or lane & 31 to fold the two ancilla halves
+// (identical until the controlled gates) onto one image.
 template <typename T, int NQ, int ENT, typename Buf>
 __device__ __forceinline__ void prefix_registers(const double* __restrict__ theta, int layers, Buf S, T* trig,
-                                                 int lane, T* re, T* im) {
+                                                 int lane, int slot_lane, T* re, T* im) {
     constexpr int R = Lay<NQ, false>::R;
     rotation_table<T>(theta, NQ * layers, trig, lane);
 #pragma unroll
@@ -67,9 +69,9 @@ __device__ __forceinline__ void prefix_registers(const double* __restrict__ thet
         im[r] = (T)0;
     }
     if constexpr (ENT == DVQ_ENT_CZ_LADDER)
-        forward_layers<T, NQ>(re, im, S, trig, layers, lane);
+        forward_layers<T, NQ>(re, im, S, trig, layers, slot_lane);
     else
-        forward_layers_ladder<T, NQ>(re, im, S, trig, layers, lane);
+        forward_layers_ladder<T, NQ>(re, im, S, trig, layers, slot_lane);
 }
 
 template <typename T, int NQ, int ENT>
@@ -77,7 +79,7 @@ __device__ __forceinline__ void simulate_prefix(const double* __restrict__ theta
                                                 cplx<T>* S, T* trig, int lane) {
     constexpr int R = Lay<NQ, false>::R;
     T re[R], im[R];
-    prefix_registers<T, NQ, ENT>(theta, layers, S, trig, lane, re, im);
+    prefix_registers<T, NQ, ENT>(theta, layers, S, trig, lane, lane, re, im);
     if constexpr (ENT == DVQ_ENT_CZ_LADDER) {
         if (layers & 1)
             store_state<T, NQ, true>(re, im, S, lane, 1);
@@ -208,8 +210,10 @@ __device__ __forceinline__ void measure_suffix_pair(const cplx<T>* S, SignedPerm
 
 // measure_suffix on a planar image, from the registers prefix_registers
 // left: the final state goes to LDS one component at a time (with the
-// pending ladder sign or frame).  After the real parts each lane keeps its
-// ancilla = 0 amplitudes' real parts and the real parts of the permuted
+// pending ladder sign or frame), both ancilla halves onto one image (they are
+// equal before the controlled gates; the lanes of the upper half write the
+// same values as those of the lower).  After the real parts each lane keeps
+// its ancilla = 0 amplitudes' real parts and the real parts of the permuted
 // ancilla = 1 amplitudes; with the imaginary parts it completes each pair
 // and applies the same S^dagger / H / <Z_anc> as measure_suffix.  The
 // registers are as prefix_registers left them, except that with the CNOT
@@ -237,14 +241,14 @@ __device__ __forceinline__ T measure_planar(T* re, T* im, T* P, SignedPerm sp, i
     // pad_slot(lane + 64 i) = a0 + 66 i: one base, the offsets are immediates
     const int a0 = lane + (lane >> 5);
     T a0r[KPL], gr[KPL];
-    store_final_plane<T, NQ, ENT>(re, P, layers, lane);
+    store_final_plane<T, NQ, ENT>(re, P, layers, lane & 31);
 #pragma unroll
     for (int i = 0; i < KPL; ++i) {
         a0r[i] = P[a0 + 66 * i];
-        gr[i] = P[suffix_slot(sl, N, i)];
+        gr[i] = P[suffix_slot(sl, 0, i)];
     }
     __syncthreads();  // every lane has read the real parts
-    store_final_plane<T, NQ, ENT>(im, P, layers, lane);
+    store_final_plane<T, NQ, ENT>(im, P, layers, lane & 31);
     // The gather addresses are formed again for the imaginary parts (one
     // add each) instead of being held in registers across the store above.
     SuffixLane sl2 = sl;
@@ -260,7 +264,7 @@ __device__ __forceinline__ T measure_planar(T* re, T* im, T* P, SignedPerm sp, i
     if (!odd) {
 #pragma unroll
         for (int i = 0; i < KPL; ++i) {
-            const T a0i = P[a0 + 66 * i], gi = P[suffix_slot(sl2, N, i)];
+            const T a0i = P[a0 + 66 * i], gi = P[suffix_slot(sl2, 0, i)];
             const T sgn = (__popc((unsigned)(i & sl.zh)) & 1) ? (T)-1 : (T)1;
             z = fmat(sgn, fmat(a0r[i], gr[i], a0i * gi), z);
         }
@@ -268,7 +272,7 @@ __device__ __forceinline__ T measure_planar(T* re, T* im, T* P, SignedPerm sp, i
     } else {
 #pragma unroll
         for (int i = 0; i < KPL; ++i) {
-            const T a0i = P[a0 + 66 * i], gi = P[suffix_slot(sl2, N, i)];
+            const T a0i = P[a0 + 66 * i], gi = P[suffix_slot(sl2, 0, i)];
             const T sgn = (__popc((unsigned)(i & sl.zh)) & 1) ? (T)-1 : (T)1;
             z = fmat(sgn, fmat(a0i, gr[i], -(a0r[i] * gi)), z);
         }
@@ -362,16 +366,16 @@ __device__ __forceinline__ T measure_planar_bvec(T* re, T* im, T* P, dvq_pauli p
     // barrier rather than held in registers across the plane stores.
     const int a0 = lane + (lane >> 5);
     const int bm = lane ^ (int)(pm.x & 63u), xhm = (int)(pm.x >> 6);
-    int um = N + (N >> 5) + bm + (bm >> 5);
+    int um = bm + (bm >> 5);
     T a0r[KPL], a0i[KPL], ur[KPL], ui[KPL];
-    store_final_plane<T, NQ, ENT>(re, P, layers, lane);
+    store_final_plane<T, NQ, ENT>(re, P, layers, lane & 31);
 #pragma unroll
     for (int i = 0; i < KPL; ++i) {
         a0r[i] = P[a0 + 66 * i];
         ur[i] = P[um + 66 * (i ^ xhm)];
     }
     __syncthreads();  // every lane has read the real parts
-    store_final_plane<T, NQ, ENT>(im, P, layers, lane);
+    store_final_plane<T, NQ, ENT>(im, P, layers, lane & 31);
     asm volatile("" : "+v"(um));
 #pragma unroll
     for (int i = 0; i < KPL; ++i) {
@@ -420,16 +424,15 @@ __device__ __forceinline__ T measure_planar_bvec(T* re, T* im, T* P, dvq_pauli p
     sp.Z = pl.z;
     sp.pw = string_pow(pl);
     const SuffixLane sl = suffix_lane(sp, lane);
-    const int a1 = N + (N >> 5) + a0;  // pad_slot(N + lane + 64 i) = a1 + 66 i
     T gr[KPL];
 #pragma unroll
-    for (int i = 0; i < KPL; ++i) P[a1 + 66 * i] = ur[i];
+    for (int i = 0; i < KPL; ++i) P[a0 + 66 * i] = ur[i];
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < KPL; ++i) gr[i] = P[suffix_slot(sl, N, i)];
+    for (int i = 0; i < KPL; ++i) gr[i] = P[suffix_slot(sl, 0, i)];
     __syncthreads();  // every lane has read the real parts of A_l v
 #pragma unroll
-    for (int i = 0; i < KPL; ++i) P[a1 + 66 * i] = ui[i];
+    for (int i = 0; i < KPL; ++i) P[a0 + 66 * i] = ui[i];
     __syncthreads();
     SuffixLane sl2 = sl;
     asm volatile("" : "+v"(sl2.base));
@@ -438,15 +441,17 @@ __device__ __forceinline__ T measure_planar_bvec(T* re, T* im, T* P, dvq_pauli p
 #pragma unroll
     for (int i = 0; i < KPL; ++i) {
         const T sgn = (__popc((unsigned)(i & sl.zh)) & 1) ? (T)-1 : (T)1;
-        z_sums(a0r[i], a0i[i], gr[i], P[suffix_slot(sl2, N, i)], sgn, s1, s2);
+        z_sums(a0r[i], a0i[i], gr[i], P[suffix_slot(sl2, 0, i)], sgn, s1, s2);
     }
     return (T)2 * wave_sum(fmat(ph.c, s1, ph.d * s2));
 }
 
-// Literal form: one wavefront simulates one circuit, every gate, on the
-// planar LDS image (half the LDS of an interleaved one, so the register
-// count sets the occupancy).  Float32, n <= 10: five wavefronts per SIMD for
-// b = |+> (96 VGPRs; the 8.6 KB image then allows 18 per CU), four for a
+// Literal form: one wavefront simulates one circuit, every gate (both
+// ancilla halves in registers).  Until the controlled gates the two halves
+// hold the same amplitudes, so the layout swaps and the final measurement go
+// through one planar image of a single half (N + N/32 values, 4.2 KB in
+// float32 at n = 10): the register count alone sets the occupancy.  Float32,
+// n <= 10: five wavefronts per SIMD for b = |+> (96 VGPRs), four for a
 // general b (126 VGPRs), both ladders, no spill; larger states and float64
 // take no bound (a bound would spill heavily).
 template <typename T, int NQ, int ENT, bool BVEC>
@@ -470,7 +475,7 @@ __device__ __forceinline__ int64_t xcd_contiguous(int64_t b, int64_t G) {
 template <typename T, int NQ, int ENT, bool BVEC>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(fast_waves<T, NQ, ENT, BVEC>()))) k_terms_fast(TermsArgs g) {
     constexpr int N = 1 << NQ;
-    constexpr int NSLOT = 2 * N + (2 * N) / 32;
+    constexpr int NSLOT = N + N / 32;  // one ancilla half (the halves are folded)
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x;
     const int P = NQ * g.layers;
@@ -485,11 +490,11 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(fast_wa
     T* trig = Pl + NSLOT;
     constexpr int R = Lay<NQ, false>::R;
     T re[R], im[R];
-    prefix_registers<T, NQ, ENT>(g.theta + row * P, g.layers, Pl, trig, lane, re, im);
+    prefix_registers<T, NQ, ENT>(g.theta + row * P, g.layers, Pl, trig, lane, lane & 31, re, im);
     // the measurements start in layout LO (true frame for the CNOT ladder);
     // once here rather than in each, so both share one register assignment
     if constexpr (ENT != DVQ_ENT_CZ_LADDER)
-        if (g.layers & 1) relayout_ladder<T, NQ, true>(re, im, Pl, lane);  // HI ladder frame -> LO true frame
+        if (g.layers & 1) relayout_ladder<T, NQ, true>(re, im, Pl, lane & 31);  // HI ladder frame -> LO true frame
     T z;
     if (BVEC && t.type == kDelta) {
         z = measure_planar_bvec<T, NQ, ENT>(re, im, Pl, g.strings[t.l], g.strings[t.m], t.j, g.b, t.part,
@@ -541,10 +546,12 @@ __global__ void __launch_bounds__(64) k_terms_shared(TermsArgs g, int64_t chunk,
     }
 }
 
+// LDS of the literal kernel (planar, folded: N (+ pad) values and the
+// rotation table) or of the prefix-shared kernel (interleaved, both halves).
 template <typename T, int NQ>
-static size_t fast_lds_bytes(int layers, bool planar = false) {
+static size_t fast_lds_bytes(int layers, bool folded_planar = false) {
     constexpr int N = 1 << NQ;
-    return (size_t)(2 * N + (2 * N) / 32) * (planar ? sizeof(T) : sizeof(cplx<T>)) +
+    return (folded_planar ? (size_t)(N + N / 32) * sizeof(T) : (size_t)(2 * N + (2 * N) / 32) * sizeof(cplx<T>)) +
            (size_t)2 * NQ * layers * sizeof(T);
 }
 
