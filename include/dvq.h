@@ -314,8 +314,9 @@ dvq_status dvq_vqls_grad_shift_noalloc(const dvq_ansatz* ansatz, const double* t
  * One workgroup per row; n <= 12 (F32) / 11 (F64): three LDS-resident
  * vectors of 2^n amplitudes per row must fit the 160 KB of a CU, so F64 at
  * n = 12 returns DVQ_EUNSUPPORTED.  Rows at n = 10, 11 (F32) and n = 10
- * (F64), with either ladder, run as one wavefront each with both vectors in
- * registers; other shapes use the LDS vectors, 512 threads per row.
+ * (F64), with either ladder, run as four wavefronts each, every wavefront
+ * holding both vectors in registers (the Pauli sums and the gradients split
+ * between them); other shapes use the LDS vectors, 512 threads per row.
  */
 dvq_status dvq_vqls_grad_adjoint(const dvq_ansatz* ansatz, const double* theta, int32_t B,
                                  int32_t precision, const dvq_c128* coeffs,
