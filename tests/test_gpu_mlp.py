@@ -119,7 +119,7 @@ def test_warm_start_beats_random_init():
     threshold in far fewer iterations (median; never-reached counts as
     budget + 1).  Threshold per system: 1e-4 above the cost random
     initialisation reaches within the budget (and at least 1e-4), so random
-    init reaches it by construction: it is the judge."""
+    init reaches it by construction and sets the bar."""
     n, layers, L_, S, S_test = 6, 3, 16, 384, 64
     an = api.AnsatzSpec(n, layers, "cnot")
     ab = toeplitz_family(S, seed=0)
