@@ -822,19 +822,21 @@ def heleshaw_run(api, dev, reps=3, iters=200):
     torch.cuda.synchronize()
     dec_ms = (time.perf_counter() - t0) * 1e3
     L = coeffs.shape[0]
-    an_t = api.AnsatzSpec(n, 4, "cz")
-    th = torch.from_numpy(theta_uniform(an_t.P, seed=0)).to(dev)
-    beta, other = api.vqls_terms(an_t, th, strings, "local", "f32", b_kind="vector", b=bt)
-    torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        api.vqls_terms(an_t, th, strings, "local", "f32", b_kind="vector", b=bt, out=(beta, other))
-    e1.record()
-    torch.cuda.synchronize()
-    eval_ms = e0.elapsed_time(e1) / reps
+    eval_ms = {}
+    for ent in ("cz", "cnot"):
+        an_t = api.AnsatzSpec(n, 4, ent)
+        th = torch.from_numpy(theta_uniform(an_t.P, seed=0)).to(dev)
+        beta, other = api.vqls_terms(an_t, th, strings, "local", "f32", b_kind="vector", b=bt)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            api.vqls_terms(an_t, th, strings, "local", "f32", b_kind="vector", b=bt, out=(beta, other))
+        e1.record()
+        torch.cuda.synchronize()
+        eval_ms[ent] = e0.elapsed_time(e1) / reps
+        del beta, other
     circuits = api.circuit_count(n, L, "local")
-    del beta, other
 
     an = api.AnsatzSpec(n, 6, "cnot")
     ev = Evaluator(an, coeffs, strings, "f32-adjoint", b_kind="vector", b=bt)
@@ -852,9 +854,10 @@ def heleshaw_run(api, dev, reps=3, iters=200):
         fids[name] = float(api.fidelity(an, torch.from_numpy(thf).to(dev), tgt)[0])
     return {"workload": "heleshaw_n10_L256", "L": int(L), "frobenius_error": round(float(ferr), 5),
             "decompose_ms": round(dec_ms, 3),
-            "terms_fp32_cz4": {"circuits": int(circuits), "ms": round(eval_ms, 3),
-                               "circuits_per_s": round(circuits / (eval_ms * 1e-3), 1),
-                               "kernel": "k_terms_fast<float,10,cz,vector> (Householder U_b in the suffix)"},
+            **{f"terms_fp32_{ent}4": {"circuits": int(circuits), "ms": round(ms, 3),
+                                      "circuits_per_s": round(circuits / (ms * 1e-3), 1),
+                                      "kernel": f"k_terms_fast<float,10,{ent},vector> (Householder U_b in the suffix)"}
+               for ent, ms in eval_ms.items()},
             "lbfgs_fp32_adjoint_cnot6": {"iterations": it, "evaluations": tr.evals,
                                          "seconds": round(tr.seconds, 3), "cost_start": c0, "cost_final": cf,
                                          "fidelity": fids},

@@ -230,7 +230,7 @@ def test_register_adjoint_per_row_batch(ent):
         assert np.max(np.abs(g[r].cpu().numpy() - g0)) < 1e-10
 
 
-@pytest.mark.parametrize("layers", [4, 6])
+@pytest.mark.parametrize("layers", [4, 6, 8])
 def test_register_adjoint_cnot_bench_system(layers):
     """The bench system (n = 10, L = 64) with the RY + CNOT ladder, the
     ansatz of the fidelity runs: complex64 and complex128 register adjoints

@@ -96,3 +96,30 @@ def test_adjoint_cost_equals_circuit_cost_n10_L64(system):
     Cc, _ = api.vqls_cost(_gpu(c), N_, "local", beta, delta)
     Ca, _ = api.vqls_grad_adjoint(an, _gpu(th), _gpu(c), _gpu(strings), "local", "f32")
     assert abs(Ca.item() - Cc.item()) < 1e-6
+
+
+@pytest.fixture(scope="module")
+def oracle_terms_cnot8(system):
+    c, xs, zs, strings, _ = system
+    th = theta_uniform(N_ * 8, seed=1)
+    print(f"[parity] oracle: all 90112 circuits of n=10 L=64, CNOT ladder, 8 layers, on "
+          f"{_oracle_pool.workers()} processes", flush=True)
+    return th, _oracle_pool.local_terms(N_, 8, "cnot", xs, zs, th)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_every_term_cnot_8_layers_n10_L64(system, oracle_terms_cnot8, precision):
+    """The ansatz of the time-to-fidelity runs (RY + CNOT ladder, 8 layers,
+    80 angles) on the same system: all 90,112 circuits against the oracle's,
+    and the cost."""
+    c, xs, zs, strings, _ = system
+    th, (wb, wd) = oracle_terms_cnot8
+    an = api.AnsatzSpec(N_, 8, "cnot")
+    beta, delta = api.vqls_terms(an, _gpu(th), _gpu(strings), "local", precision)
+    tol = 1e-12 if precision == "f64" else 1e-5
+    eb = np.abs(beta[0].cpu().numpy() - wb)
+    ed = np.abs(delta[0].cpu().numpy() - wd)
+    assert eb.max() < tol, (precision, float(eb.max()))
+    assert ed.max() < tol, (precision, float(ed.max()))
+    C, _ = api.vqls_cost(_gpu(c), N_, "local", beta, delta)
+    assert abs(C.item() - oc.cost_from_terms(c, wb, wd, N_, "local")) < (1e-12 if precision == "f64" else 1e-6)
