@@ -600,9 +600,10 @@ def lbfgs_study(api, dev, an, coeffs, strings, theta_rand, net, plain_s, max_eva
 
 FID_LAYERS, FID_TARGET = 8, 0.9999
 FID_RECORD = os.path.join(ROOT, "profiles", "fidelity_n10_L64_cnot8_local.json")
+RACE_ITERS = 8  # L-BFGS iterations of the start race (prediction vs V|0> = b)
 
 
-def fidelity_target(api, dev, coeffs, strings, max_evals=4000, family_bins=16, family_iters=100, epochs=300):
+def fidelity_target(api, dev, coeffs, strings, max_evals=4000, family_bins=16, family_iters=100, epochs=1000):
     """Seconds to fidelity 0.9999 against x~ = A~^-1 b on the bench system
     (n = 10, L = 64), RY + CNOT ladder, 8 layers, local cost, L-BFGS-B.
 
@@ -620,13 +621,16 @@ def fidelity_target(api, dev, coeffs, strings, max_evals=4000, family_bins=16, f
       b (the centre system solved from V|0> = b; the family in 16 bins of b
       taken outward from the centre, each system started from the nearest
       solved system and each bin solved by one batched L-BFGS run on the
-      complex128 adjoint), with V|0> = b as the fallback."""
+      complex128 adjoint; the output bias initialised at the centre
+      system's solution, so the network learns each system's offset from
+      it), with V|0> = b as the fallback (kept when its complex64 cost is
+      lower than the prediction's)."""
     import numpy as np
     import torch
 
     from paper_2604_14435_amd.optim import Evaluator, lbfgs, lbfgs_refine
     from paper_2604_14435_amd.warmstart import (MLPConfig, WarmStartMLP, continuation_targets, decompose_batches,
-                                                decompose_family, toeplitz_batches)
+                                                decompose_family, race_starts, toeplitz_batches)
     from workloads import family_split, plus_state, toeplitz, toeplitz_family
 
     n = N_QUBITS
@@ -654,14 +658,15 @@ def fidelity_target(api, dev, coeffs, strings, max_evals=4000, family_bins=16, f
                              if len(idx) else None)
         return out
 
-    def run_fast(form, th0, t_extra=0.0):
+    def run_fast(form, th0, t_extra=0.0, e_extra=0):
         fast = Evaluator(an, coeffs, strings, form, kind=kind)
         precise = Evaluator(an, coeffs, strings, "f64-adjoint", kind=kind)
         fast(th0), precise(th0)  # graphs captured before the clock starts
         th, tr = lbfgs_refine(fast, precise, th0, max_evals=max_evals, gtol=1e-12)
         F = fid([th0] + tr.thetas)
-        return {"evaluations": tr.evals, "seconds": round(tr.seconds + t_extra, 4),
-                "reach": reach(F, [t_extra] + [x + t_extra for x in tr.iter_seconds], [0] + tr.iter_evals),
+        return {"evaluations": tr.evals + e_extra, "seconds": round(tr.seconds + t_extra, 4),
+                "reach": reach(F, [t_extra] + [x + t_extra for x in tr.iter_seconds],
+                               [e_extra] + [e + e_extra for e in tr.iter_evals]),
                 "start_fidelity": float(F[0]), "final_fidelity": float(F[-1]), "stop": tr.stop[:80]}
 
     out = {"system": "toeplitz_n10_L64 (a=1.0, b=-0.45), RY+CNOT ladder, %d layers (%d angles), local cost"
@@ -708,29 +713,27 @@ def fidelity_target(api, dev, coeffs, strings, max_evals=4000, family_bins=16, f
     tr_idx, te_idx = family_split(len(ab), 3584, seed=1)
     keep = tr_idx[fcost[tr_idx] <= 5.0 * np.median(fcost)]
     t0 = time.perf_counter()
-    net = WarmStartMLP(2, an.P, MLPConfig(hidden=256, epochs=epochs, batch=256, lr=1e-3), dev)
+    # the output bias starts at the centre system's solution: the network
+    # learns each system's offset from it
+    net = WarmStartMLP(2, an.P, MLPConfig(hidden=256, epochs=epochs, batch=256, lr=1e-3), dev, out_bias=th_c)
     losses = net.fit(ab[keep], torch.from_numpy(targets[keep]).to(dev))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    # per system: predict, choose between the prediction and V|0> = b by
-    # cost (complex64 adjoint), then the fast form
-    chooser = Evaluator(an, coeffs, strings, "f32-adjoint", kind=kind)
-    chooser(th_b)
+    # per system: predict, race the prediction against V|0> = b for a few
+    # L-BFGS iterations (both rows in one batched complex64 adjoint launch per
+    # evaluation), continue the winner with the fast form; the prediction,
+    # the race and its evaluations are inside the timed figures
+    race_starts(an, coeffs.view(1, -1), strings.view(1, -1, 2), th_b.reshape(1, -1), th_b, iters=RACE_ITERS)
     t0 = time.perf_counter()
     pred = net.predict(np.array([[DIAG, OFFDIAG]]))[0].cpu().numpy()
-    use_pred = chooser(pred)[0] <= chooser(th_b)[0]
+    start, used, _, race_evals = race_starts(an, coeffs.view(1, -1), strings.view(1, -1, 2), pred.reshape(1, -1),
+                                             th_b, iters=RACE_ITERS)
     t_choose = time.perf_counter() - t0
-    if use_pred:
-        out["fp32_adjoint_warm_start"] = run_fast("f32-adjoint", pred, t_extra=t_choose)
-        out["fp32_circuits_adjoint_warm_start"] = run_fast("f32", pred, t_extra=t_choose)
-    else:  # the selection kept V|0> = b: the runs from_b plus the selection time
-        for key, src in (("fp32_adjoint_warm_start", "fp32_adjoint_from_b"),
-                         ("fp32_circuits_adjoint_warm_start", "fp32_circuits_adjoint_from_b")):
-            r0 = out[src]
-            out[key] = {**r0, "seconds": round(r0["seconds"] + t_choose, 4),
-                        "reach": {k: (None if v is None else {**v, "seconds": round(v["seconds"] + t_choose, 4)})
-                                  for k, v in r0["reach"].items()},
-                        "start": "V|0> = b (the selection kept it); the %s run plus the selection" % src}
+    use_pred = bool(used[0])
+    for key, form in (("fp32_adjoint_warm_start", "f32-adjoint"), ("fp32_circuits_adjoint_warm_start", "f32")):
+        out[key] = run_fast(form, start[0], t_extra=t_choose, e_extra=race_evals)
+        out[key]["start"] = ("race of %d L-BFGS iterations (%d evaluations, %.4f s incl. the prediction), won by %s"
+                             % (RACE_ITERS, race_evals, t_choose, "the prediction" if use_pred else "V|0> = b"))
     # the same choice on 64 held-out systems of the family (costs only)
     held = te_idx[:64]
     hp = net.predict(ab[held]).cpu().numpy()
@@ -739,8 +742,37 @@ def fidelity_target(api, dev, coeffs, strings, max_evals=4000, family_bins=16, f
     bev = BatchEvaluator(an, fc[torch.from_numpy(held).to(dev)].contiguous(),
                          fs[torch.from_numpy(held).to(dev)].contiguous(), "f32", kind)
     cp_, cb_ = bev(hp)[0], bev(hb)[0]
+    # 12 of them solved to the target from V|0> = b and from the race's
+    # winner (fidelity against each system's own x~, complex64 adjoint then
+    # complex128; the race's evaluations counted)
+    h12 = torch.from_numpy(held[:12]).to(dev)
+    hstart, hused, _, h_race_evals = race_starts(an, fc[h12].contiguous(), fs[h12].contiguous(), hp[:12], th_b,
+                                                 iters=RACE_ITERS)
+    evals_b, evals_w, f0_w = [], [], []
+    for i, j in enumerate(held[:12]):
+        cj, sj = fc[int(j)], fs[int(j)]
+        Aj = api.pauli_sum_dense(cj, sj, n).real.cpu().numpy()
+        xj = np.linalg.solve(Aj, bvec)
+        tj = torch.from_numpy((xj / np.linalg.norm(xj)).astype(np.complex128)).to(dev)
+        for name, th0, e0_ in (("b", th_b, 0), ("race", hstart[i], h_race_evals)):
+            _, trj = lbfgs_refine(Evaluator(an, cj, sj, "f32-adjoint", kind=kind),
+                                  Evaluator(an, cj, sj, "f64-adjoint", kind=kind), th0, max_evals=max_evals,
+                                  gtol=1e-12)
+            Fj = api.fidelity(an, torch.from_numpy(np.stack([th0] + trj.thetas)).to(dev), tj).cpu().numpy()
+            hit = np.nonzero(Fj >= FID_TARGET)[0]
+            e = int(([0] + trj.iter_evals)[hit[0]]) + e0_ if len(hit) else None
+            (evals_b if name == "b" else evals_w).append(e)
+            if name == "race":
+                f0_w.append(float(Fj[0]))
     out["warm_start"] = {"prediction_used": bool(use_pred), "prediction_fidelity": float(fid([pred])[0]),
                          "start_fidelity_b": float(fid([th_b])[0]),
+                         "held_out_12_evaluations_to_target": {
+                             "from_b": evals_b, "from_chosen_start": evals_w,
+                             "race_won_by_prediction": [bool(u) for u in hused], "race_evaluations": h_race_evals,
+                             "chosen_start_fidelity": [round(f, 6) for f in f0_w],
+                             "median_from_b": float(np.median([e for e in evals_b if e is not None] or [np.nan])),
+                             "median_from_chosen_start": float(np.median([e for e in evals_w if e is not None]
+                                                                         or [np.nan]))},
                          "held_out_64": {"prediction_chosen": float(np.mean(cp_ <= cb_)),
                                          "median_cost_prediction": float(np.median(cp_)),
                                          "median_cost_b_start": float(np.median(cb_))},

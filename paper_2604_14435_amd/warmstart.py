@@ -127,21 +127,25 @@ class WarmStartMLP:
     (dvq_feature_stats) and applied inside the kernels; Python only draws
     the epoch's row permutation (host generator) and orders the calls."""
 
-    def __init__(self, d_in: int, d_out: int, cfg: MLPConfig = MLPConfig(), device="cuda:0"):
+    def __init__(self, d_in: int, d_out: int, cfg: MLPConfig = MLPConfig(), device="cuda:0", out_bias=None):
+        """`out_bias` (length d_out) initialises the output layer's bias: with
+        the solution of a reference system there, training fits each
+        system's offset from that solution rather than its absolute angles."""
         if d_in > 32 or d_out > 128 or cfg.hidden not in (64, 128, 256):
             raise ValueError("the fused MLP kernels take d_in <= 32, d_out <= 128, hidden 64/128/256")
         self.cfg = cfg
         self.device = torch.device(device)
         self.shape = api.mlp_shape(d_in, cfg.hidden, d_out)
-        self.params = self.init_params(d_in, cfg.hidden, d_out, cfg.seed).to(self.device)
+        self.params = self.init_params(d_in, cfg.hidden, d_out, cfg.seed, out_bias).to(self.device)
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
         self.t = 0
         self.stats = None  # (mean, 1/std) of the training inputs, device float32
 
     @staticmethod
-    def init_params(d_in: int, hidden: int, d_out: int, seed: int) -> torch.Tensor:
-        """He-uniform weights, zero biases, packed W1, b1, W2, b2, W3, b3."""
+    def init_params(d_in: int, hidden: int, d_out: int, seed: int, out_bias=None) -> torch.Tensor:
+        """He-uniform weights, zero biases (b3 = out_bias when given), packed
+        W1, b1, W2, b2, W3, b3."""
         rng = np.random.default_rng(seed)
 
         def w(o, i):
@@ -149,8 +153,9 @@ class WarmStartMLP:
             return rng.uniform(-lim, lim, size=(o, i)).astype(np.float32).ravel()
 
         z = lambda k: np.zeros(k, dtype=np.float32)
+        b3 = z(d_out) if out_bias is None else np.asarray(out_bias, dtype=np.float32).reshape(d_out)
         flat = np.concatenate([w(hidden, d_in), z(hidden), w(hidden, hidden), z(hidden),
-                               w(d_out, hidden), z(d_out)])
+                               w(d_out, hidden), b3])
         return torch.from_numpy(flat)
 
     def fit(self, X, T, epochs: int | None = None):
@@ -193,6 +198,28 @@ def choose_start(ansatz, coeffs, strings, theta_pred, theta_rand, kind="local", 
     Cr, _ = api.vqls_grad_adjoint(ansatz, theta_rand, coeffs, strings, kind, precision, per_row_system=True)
     use = torch.isfinite(Cp) & (Cp <= Cr)
     return torch.where(use.unsqueeze(1), theta_pred, theta_rand), use
+
+
+def race_starts(ansatz: api.AnsatzSpec, coeffs: torch.Tensor, strings: torch.Tensor, theta_pred: np.ndarray,
+                theta_ref: np.ndarray, iters: int = 8, kind: str = "local", precision: str = "f32"):
+    """Start selection by a short race: for every system (coeffs [S, L],
+    strings [S, L, 2]) both starts, the prediction and the reference (e.g.
+    V|0> = b), take `iters` L-BFGS iterations together (one batched adjoint
+    launch per evaluation of all 2S rows); each system keeps the run that
+    reached the lower cost.  A start whose cost is lower is not always the
+    one that converges sooner, which the race settles at a small fixed cost.
+    Returns (theta [S, P], the winning runs' iterates; used_prediction [S]
+    bool; C [S], their costs; evaluations of the batched race)."""
+    from .optim import BatchEvaluator, lbfgs_batched
+
+    S = coeffs.shape[0]
+    both = np.concatenate([np.asarray(theta_pred, dtype=np.float64).reshape(S, -1),
+                           np.broadcast_to(np.asarray(theta_ref, dtype=np.float64), (S, ansatz.P))])
+    ev = BatchEvaluator(ansatz, torch.cat([coeffs, coeffs]).contiguous(), torch.cat([strings, strings]).contiguous(),
+                        precision, kind)
+    th, C = lbfgs_batched(ev, both, iters=iters)
+    use = np.isfinite(C[:S]) & (C[:S] <= C[S:])
+    return np.where(use[:, None], th[:S], th[S:]), use, np.where(use, C[:S], C[S:]), ev.evals
 
 
 def continuation_targets(ansatz: api.AnsatzSpec, ab: np.ndarray, coeffs: torch.Tensor, strings: torch.Tensor,

@@ -248,3 +248,34 @@ def test_fused_train_step_ignores_rows_outside_x():
         outs.append((params.clone(), g.clone()))
     for p_, g_ in outs[1:]:
         assert torch.equal(p_, outs[0][0]) and torch.equal(g_, outs[0][1])
+
+
+def test_race_starts_keeps_the_better_run():
+    """race_starts: per system, the run (prediction or reference) with the
+    lower cost after a few batched L-BFGS iterations; the returned angles
+    are that run's iterate and the returned costs are its costs."""
+    from paper_2604_14435_amd.optim import BatchEvaluator, Evaluator, lbfgs
+    from paper_2604_14435_amd.warmstart import race_starts
+
+    n, layers = 4, 4
+    an = api.AnsatzSpec(n, layers, "cnot")
+    dev = "cuda:0"
+    cs, ss = [], []
+    for b in (-0.2, -0.3, -0.4):
+        c, s, _ = api.pauli_decompose(torch.from_numpy(toeplitz(n, 1.0, b)).to(dev), top_L=8)
+        cs.append(c)
+        ss.append(s)
+    coeffs, strings = torch.stack(cs).contiguous(), torch.stack(ss).contiguous()
+    near = np.stack([lbfgs(Evaluator(an, coeffs[i], strings[i], "f64-adjoint"), theta_uniform(an.P, seed=i),
+                           max_evals=400)[0] for i in range(3)])
+    far = np.stack([theta_uniform(an.P, seed=50 + i) for i in range(3)])
+    # a near-solution prediction wins against a random reference ...
+    th, used, C, evals = race_starts(an, coeffs, strings, near, far[0], iters=5)
+    assert used.all() and evals >= 6
+    C_chk, _ = BatchEvaluator(an, coeffs, strings, "f32", "local")(th)
+    assert np.allclose(C, C_chk, rtol=0, atol=1e-12)
+    C_near, _ = BatchEvaluator(an, coeffs, strings, "f32", "local")(near)
+    assert np.all(C <= C_near + 1e-7)
+    # ... and loses when the roles are swapped
+    th2, used2, _, _ = race_starts(an, coeffs, strings, far, near[0], iters=5)
+    assert not used2[0]
