@@ -14,6 +14,27 @@ struct Term {
     int l, m;  // term indices (m unused for gamma)
 };
 
+// floor(n / d) for 0 <= n < 2^31 as one 64-bit multiply and shift.  With
+// s = ceil(log2 d) and m = floor(2^(31+s) / d) + 1, 2^(31+s) < m d <=
+// 2^(31+s) + 2^s, so floor(m n / 2^(31+s)) = floor(n / d) for every such n
+// (Granlund and Montgomery, division by invariant integers); m < 2^33 and
+// m n < 2^64.  The kernels' circuit indices are wave-uniform, so this runs on
+// the scalar unit instead of a 64-bit division expansion on the vector unit.
+struct DivBy {
+    uint64_t m;
+    int shift;  // 31 + s
+};
+
+inline DivBy div_by(uint32_t d) {
+    int s = 0;
+    while ((uint64_t(1) << s) < d) ++s;
+    return {(uint64_t(1) << (31 + s)) / d + 1, 31 + s};
+}
+
+__device__ __forceinline__ uint32_t div_fast(uint32_t n, const DivBy& D) {
+    return (uint32_t)(((uint64_t)n * D.m) >> D.shift);
+}
+
 // Arguments of one dvq_vqls_terms launch (passed by value to the kernels).
 struct TermsArgs {
     const double* theta;
@@ -25,7 +46,23 @@ struct TermsArgs {
     int64_t c0;       // first circuit (in decode_term order) of each row's range
     int64_t per_row;  // circuits per row in this launch: c0 .. c0 + per_row - 1
     int64_t total;    // per_row * B
+    // divisors of the index decode when c0 + per_row and total are below
+    // 2^31 (fast_div = 1; set by with_fast_div just before a launch)
+    DivBy div_row, div_L2, div_L;
+    int fast_div;
 };
+
+// g with the decode divisors filled in (fast_div = 0 past 2^31 circuits).
+inline TermsArgs with_fast_div(TermsArgs g) {
+    const int64_t lim = int64_t(1) << 31;
+    g.fast_div = (g.total < lim && g.c0 + g.per_row < lim && g.per_row > 0) ? 1 : 0;
+    if (g.fast_div) {
+        g.div_row = div_by((uint32_t)g.per_row);
+        g.div_L2 = div_by((uint32_t)((int64_t)g.L * g.L));
+        g.div_L = div_by((uint32_t)g.L);
+    }
+    return g;
+}
 
 // The same launch restricted to circuits first .. first + count - 1 of each
 // row (first and count even: whole Re/Im pairs).
@@ -64,6 +101,33 @@ __host__ __device__ __forceinline__ Term decode_term(int64_t c, int L, int n, in
         t.m = 0;
     }
     (void)n;
+    return t;
+}
+
+// decode_term for c < 2^31 with the launch's divisors (same order).
+__device__ __forceinline__ Term decode_term_fast(uint32_t c, const TermsArgs& g) {
+    Term t;
+    t.part = (int)(c & 1u);
+    const uint32_t u = c >> 1;
+    const uint32_t L = (uint32_t)g.L, L2 = L * L;
+    if (g.kind == DVQ_COST_LOCAL) {
+        const uint32_t jj = div_fast(u, g.div_L2);
+        const uint32_t lm = u - jj * L2;
+        t.type = jj == 0 ? kBeta : kDelta;
+        t.j = (int)jj - 1;
+        t.l = (int)div_fast(lm, g.div_L);
+        t.m = (int)(lm - (uint32_t)t.l * L);
+    } else if (u < L2) {
+        t.type = kBeta;
+        t.j = -1;
+        t.l = (int)div_fast(u, g.div_L);
+        t.m = (int)(u - (uint32_t)t.l * L);
+    } else {
+        t.type = kGamma;
+        t.j = -1;
+        t.l = (int)(u - L2);
+        t.m = 0;
+    }
     return t;
 }
 

@@ -483,8 +483,16 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(fast_wa
     const int64_t gid = xcd_contiguous((int64_t)blockIdx.x + (int64_t)blockIdx.y * gridDim.x,
                                        (int64_t)gridDim.x * gridDim.y);
     if (gid >= g.total) return;
-    const int64_t row = gid / g.per_row;
-    const Term t = decode_term(g.c0 + gid - row * g.per_row, g.L, NQ, g.kind);
+    int64_t row;
+    Term t;
+    if (g.fast_div) {
+        const uint32_t r = div_fast((uint32_t)gid, g.div_row);
+        row = r;
+        t = decode_term_fast((uint32_t)g.c0 + (uint32_t)gid - r * (uint32_t)g.per_row, g);
+    } else {
+        row = gid / g.per_row;
+        t = decode_term(g.c0 + gid - row * g.per_row, g.L, NQ, g.kind);
+    }
 
     T* Pl = reinterpret_cast<T*>(smem);
     T* trig = Pl + NSLOT;
@@ -559,7 +567,7 @@ template <typename T, int NQ, int ENT, bool BVEC>
 static dvq_status launch_fast_ent(const TermsArgs& g, hipStream_t s) {
     const size_t lds = fast_lds_bytes<T, NQ>(g.layers, true);
     DVQ_TRY_HIP(allow_lds((const void*)k_terms_fast<T, NQ, ENT, BVEC>, lds));
-    hipLaunchKernelGGL((k_terms_fast<T, NQ, ENT, BVEC>), grid_for(g.total), dim3(64), lds, s, g);
+    hipLaunchKernelGGL((k_terms_fast<T, NQ, ENT, BVEC>), grid_for(g.total), dim3(64), lds, s, with_fast_div(g));
     DVQ_CHECK_LAUNCH("k_terms_fast");
     return DVQ_OK;
 }
