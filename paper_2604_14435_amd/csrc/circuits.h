@@ -143,6 +143,21 @@ __device__ __forceinline__ void store_term(const TermsArgs& g, int64_t row, cons
     reinterpret_cast<double*>(dst)[t.part] = z;
 }
 
+// Both parts of term t (the real-part and imaginary-part circuits) in one
+// 16-byte store.
+__device__ __forceinline__ void store_term_pair(const TermsArgs& g, int64_t row, const Term& t, double re_part,
+                                                double im_part) {
+    const int64_t L2 = (int64_t)g.L * g.L;
+    dvq_c128* dst;
+    if (t.type == kBeta)
+        dst = g.beta + row * L2 + (int64_t)t.l * g.L + t.m;
+    else if (t.type == kDelta)
+        dst = g.other + row * (int64_t)g.n * L2 + (int64_t)t.j * L2 + (int64_t)t.l * g.L + t.m;
+    else
+        dst = g.other + row * (int64_t)g.L + t.l;
+    *dst = dvq_c128{re_part, im_part};
+}
+
 // 2-D grid of at least `total` workgroups (x at most 65536), as few extra
 // (immediately exiting) workgroups as possible: gy rows of gx.
 inline dim3 grid_for(int64_t total) {

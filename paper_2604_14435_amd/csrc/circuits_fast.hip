@@ -59,10 +59,9 @@ namespace dvq {
 // `slot_lane`: the lane itself, or lane & 31 to fold the two ancilla halves
 // (identical until the controlled gates) onto one image.
 template <typename T, int NQ, int ENT, typename Buf>
-__device__ __forceinline__ void prefix_registers(const double* __restrict__ theta, int layers, Buf S, T* trig,
-                                                 int lane, int slot_lane, T* re, T* im) {
+__device__ __forceinline__ void prefix_from_table(int layers, Buf S, const T* trig, int lane, int slot_lane, T* re,
+                                                  T* im) {
     constexpr int R = Lay<NQ, false>::R;
-    rotation_table<T>(theta, NQ * layers, trig, lane);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         re[r] = (r == 0 && (lane & 31) == 0) ? (T)0.70710678118654752440 : (T)0;
@@ -72,6 +71,13 @@ __device__ __forceinline__ void prefix_registers(const double* __restrict__ thet
         forward_layers<T, NQ>(re, im, S, trig, layers, slot_lane);
     else
         forward_layers_ladder<T, NQ>(re, im, S, trig, layers, slot_lane);
+}
+
+template <typename T, int NQ, int ENT, typename Buf>
+__device__ __forceinline__ void prefix_registers(const double* __restrict__ theta, int layers, Buf S, T* trig,
+                                                 int lane, int slot_lane, T* re, T* im) {
+    rotation_table<T>(theta, NQ * layers, trig, lane);
+    prefix_from_table<T, NQ, ENT>(layers, S, trig, lane, slot_lane, re, im);
 }
 
 template <typename T, int NQ, int ENT>
@@ -460,6 +466,14 @@ constexpr int fast_waves() {
     return BVEC ? 4 : 5;
 }
 
+// Circuits per wavefront of the literal kernel: the two circuits of one term
+// (b = |+>) share the rotation parameters; the float32 CNOT-ladder and the
+// general-b kernels keep one (the second pass spills or slows them).
+template <typename T, int ENT, bool BVEC>
+constexpr int circuits_per_wave() {
+    return (BVEC || (ENT == DVQ_ENT_CNOT_LADDER && sizeof(T) == 4)) ? 1 : 2;
+}
+
 // Workgroup b of a launch runs on XCD b mod 8: the dispatcher deals
 // workgroups to the eight XCDs in turn, and each XCD has its own L2.  Mapping
 // each XCD's workgroups to one contiguous range of circuits keeps neighbouring
@@ -480,8 +494,14 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(fast_wa
     const int lane = threadIdx.x;
     const int P = NQ * g.layers;
 
-    const int64_t gid = xcd_contiguous((int64_t)blockIdx.x + (int64_t)blockIdx.y * gridDim.x,
+    // With two circuits per wavefront, one wavefront per term: its
+    // real-part and imaginary-part circuits, each simulated from |0> gate by
+    // gate; only the rotation parameters (a function of theta alone) are
+    // computed once for both.
+    constexpr int CPW = circuits_per_wave<T, ENT, BVEC>();
+    const int64_t pid = xcd_contiguous((int64_t)blockIdx.x + (int64_t)blockIdx.y * gridDim.x,
                                        (int64_t)gridDim.x * gridDim.y);
+    const int64_t gid = CPW * pid;  // c0 and per_row are even: a pair lies in one row and one term
     if (gid >= g.total) return;
     int64_t row;
     Term t;
@@ -497,21 +517,38 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(fast_wa
     T* Pl = reinterpret_cast<T*>(smem);
     T* trig = Pl + NSLOT;
     constexpr int R = Lay<NQ, false>::R;
-    T re[R], im[R];
-    prefix_registers<T, NQ, ENT>(g.theta + row * P, g.layers, Pl, trig, lane, lane & 31, re, im);
-    // the measurements start in layout LO (true frame for the CNOT ladder);
-    // once here rather than in each, so both share one register assignment
-    if constexpr (ENT != DVQ_ENT_CZ_LADDER)
-        if (g.layers & 1) relayout_ladder<T, NQ, true>(re, im, Pl, lane & 31);  // HI ladder frame -> LO true frame
-    T z;
-    if (BVEC && t.type == kDelta) {
-        z = measure_planar_bvec<T, NQ, ENT>(re, im, Pl, g.strings[t.l], g.strings[t.m], t.j, g.b, t.part,
-                                            g.layers, lane);
+    if constexpr (CPW == 1) {
+        T re[R], im[R];
+        prefix_registers<T, NQ, ENT>(g.theta + row * P, g.layers, Pl, trig, lane, lane & 31, re, im);
+        // the measurements start in layout LO (true frame for the CNOT
+        // ladder); once here rather than in each, so both share one register
+        // assignment
+        if constexpr (ENT != DVQ_ENT_CZ_LADDER)
+            if (g.layers & 1) relayout_ladder<T, NQ, true>(re, im, Pl, lane & 31);  // HI ladder frame -> LO true frame
+        T z;
+        if (BVEC && t.type == kDelta) {
+            z = measure_planar_bvec<T, NQ, ENT>(re, im, Pl, g.strings[t.l], g.strings[t.m], t.j, g.b, t.part,
+                                                g.layers, lane);
+        } else {
+            const SignedPerm sp = suffix_perm(g.strings[t.l], g.strings[t.m], t.type, t.j);
+            z = measure_planar<T, NQ, ENT>(re, im, Pl, sp, t.part, g.layers, lane);
+        }
+        if (lane == 0) store_term(g, row, t, (double)z);
     } else {
-        const SignedPerm sp = suffix_perm(g.strings[t.l], g.strings[t.m], t.type, t.j);
-        z = measure_planar<T, NQ, ENT>(re, im, Pl, sp, t.part, g.layers, lane);
+        rotation_table<T>(g.theta + row * P, P, trig, lane);  // ends with a barrier
+        T zp[2];
+#pragma unroll 1
+        for (int part = 0; part < 2; ++part) {
+            T re[R], im[R];
+            prefix_from_table<T, NQ, ENT>(g.layers, Pl, trig, lane, lane & 31, re, im);
+            if constexpr (ENT != DVQ_ENT_CZ_LADDER)
+                if (g.layers & 1) relayout_ladder<T, NQ, true>(re, im, Pl, lane & 31);
+            const SignedPerm sp = suffix_perm(g.strings[t.l], g.strings[t.m], t.type, t.j);
+            zp[part] = measure_planar<T, NQ, ENT>(re, im, Pl, sp, part, g.layers, lane);
+            __syncthreads();  // the image is rewritten by the next circuit's first layout swap
+        }
+        if (lane == 0) store_term_pair(g, row, t, (double)zp[0], (double)zp[1]);
     }
-    if (lane == 0) store_term(g, row, t, (double)z);
 }
 
 // Prefix-shared form: one wavefront simulates the common prefix (H, V(theta))
@@ -567,7 +604,10 @@ template <typename T, int NQ, int ENT, bool BVEC>
 static dvq_status launch_fast_ent(const TermsArgs& g, hipStream_t s) {
     const size_t lds = fast_lds_bytes<T, NQ>(g.layers, true);
     DVQ_TRY_HIP(allow_lds((const void*)k_terms_fast<T, NQ, ENT, BVEC>, lds));
-    hipLaunchKernelGGL((k_terms_fast<T, NQ, ENT, BVEC>), grid_for(g.total), dim3(64), lds, s, with_fast_div(g));
+    if ((g.c0 | g.per_row) & 1) return fail(DVQ_EINVAL, "circuit range not whole Re/Im pairs");
+    constexpr int CPW = circuits_per_wave<T, ENT, BVEC>();
+    hipLaunchKernelGGL((k_terms_fast<T, NQ, ENT, BVEC>), grid_for(g.total / CPW), dim3(64), lds, s,
+                       with_fast_div(g));
     DVQ_CHECK_LAUNCH("k_terms_fast");
     return DVQ_OK;
 }
