@@ -466,12 +466,14 @@ constexpr int fast_waves() {
     return BVEC ? 4 : 5;
 }
 
-// Circuits per wavefront of the literal kernel: the two circuits of one term
-// (b = |+>) share the rotation parameters; the float32 CNOT-ladder and the
-// general-b kernels keep one (the second pass spills or slows them).
+// Circuits per wavefront of the literal kernel: in float64 (b = |+>) the two
+// circuits of one term share the rotation parameters, 2 % faster per
+// evaluation.  The float32 kernels keep one: with two, the CNOT ladder spills,
+// the CZ ladder gained 0.5 % while its result writes left the L2s as 4.6 times
+// the result bytes, and the general-b kernels would not fit their registers.
 template <typename T, int ENT, bool BVEC>
 constexpr int circuits_per_wave() {
-    return (BVEC || (ENT == DVQ_ENT_CNOT_LADDER && sizeof(T) == 4)) ? 1 : 2;
+    return (BVEC || sizeof(T) == 4) ? 1 : 2;
 }
 
 // Workgroup b of a launch runs on XCD b mod 8: the dispatcher deals
