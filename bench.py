@@ -26,6 +26,7 @@ per second of whole-iteration wall time of the fast form.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import math
 import os
@@ -218,7 +219,7 @@ def mlp_timing(api, dev, d_in=2, H=256, D=40, B=256, family=4096, reps=200):
     def infer(_):
         api.mlp_forward(shape, params, Xf, out=ffam)
 
-    # fused forms: one training step = 2 launches (rows of a 3584-row
+    # fused forms: one training step = 3 launches (rows of a 3584-row
     # training set picked by an index array, inputs standardised on the
     # device), one forward pass = 1 launch
     Xtr = torch.randn(3584, d_in, generator=g).to(dev)
@@ -257,7 +258,8 @@ def mlp_timing(api, dev, d_in=2, H=256, D=40, B=256, family=4096, reps=200):
     res["peak_tflops"] = BF16_MFMA_PEAK
     res["shape"] = f"{d_in}->{H}->{H}->{D}, bfloat16 operands, float32 accumulation"
     res["kernels"] = {"unfused": "k_gemm_bf16 per GEMM, k_loss_grad, k_colsum, k_adamw (>= 8 launches per step)",
-                      "fused": "k_mlp_train_chunk (32 rows per workgroup) + k_mlp_reduce_adamw; k_mlp_predict"}
+                      "fused": "k_mlp_weights_bf16 + k_mlp_train_chunk (32 rows per workgroup) + "
+                               "k_mlp_reduce_adamw; k_mlp_predict"}
     return res
 
 
@@ -1213,11 +1215,16 @@ def main() -> int:
     del fg
     # the same steps launched eagerly, with HIP events around every circuit
     # kernel: the roofline's kernel time
+    gc.collect()  # the graphs' teardown stays out of the timed steps
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
+    marks = [t0]
     for _ in range(args.steps):
         fast_step(theta, True)
+        marks.append(time.perf_counter())
     torch.cuda.synchronize()
     eager_s = (time.perf_counter() - t0) / args.steps
+    enqueue_ms = sorted((b - a) * 1e3 for a, b in zip(marks, marks[1:]))  # host time to launch each step
     kern_ms = sum(a.elapsed_time(b) for a, b in ev) / len(ev)
 
     progress(f"fast form: {fast_s * 1e3:.3f} ms per iteration (graphs), {eager_s * 1e3:.3f} eager")
@@ -1352,6 +1359,8 @@ def main() -> int:
                             "fp32_adjoint_eager_launches": round(eager_s, 6)},
         "fast_step": {"launch": f"HIP graphs of {GRAPH_UNROLL} iterations (alternating term buffers), replayed",
                       "eager_ramp": {"seconds": args.ramp_s, "steps": ramp_steps},
+                      "eager_enqueue_ms_per_step": {"median": round(enqueue_ms[len(enqueue_ms) // 2], 4),
+                                                    "max": round(enqueue_ms[-1], 4)},
                       "adjoint_alone_ms": round(adjoint_ms, 4)},
         "circuits_per_s": {"fp32_adjoint": round(circuits / fast_s, 1),
                            "plain_fp64_shift": round(plain_circuits / plain_s, 1)},

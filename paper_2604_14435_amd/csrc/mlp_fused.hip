@@ -10,11 +10,13 @@
 // keeps that chunk's activations in LDS as bfloat16, row-major where they
 // are the A operand of a product and transposed where the batch index is
 // the contraction index (the weight-gradient products), so every operand
-// fragment is one 16-byte LDS read.  The forward pass reads the weights from
-// the float32 master copy (L2-resident, 77 K parameters) and rounds them as
-// they are loaded; the training step first makes a bfloat16 copy laid out so
-// that every weight fragment of the step is one 16-byte load (W2 and W3 also
-// transposed for the backward products).  Everything a chunk contributes to
+// fragment is one 16-byte LDS read.  The inference pass reads the weights
+// from the float32 master copy (L2-resident, 77 K parameters) and rounds them
+// as they are loaded; the training step first makes a bfloat16 copy laid out
+// so that every weight fragment of the step is one 16-byte load (W2 and W3
+// also transposed for the backward products), and each wavefront of a chunk
+// loads the fragments of its output columns one phase ahead of their use.
+// Everything a chunk contributes to
 // the gradient is a sum over its own rows, so the backward pass needs no
 // other chunk: each workgroup writes its partial gradient; the last launch
 // sums the partials in chunk order (bit-reproducible) and applies AdamW.
@@ -141,12 +143,11 @@ __device__ __forceinline__ float tile_colsum(f32x4 v) {
     return s;
 }
 
-// Forward pass of one chunk: xs/xT, h1/h1T, h2/h2T in LDS; returns nothing,
-// leaves the layer-3 tiles to the caller (epilogue differs between training
-// and inference).
-template <int H, bool PRE>
+// Inference forward pass of one chunk up to layer 2: xs/xT, h1/h1T, h2/h2T
+// in LDS, weights rounded from the float32 master copy as they are loaded.
+template <int H>
 __device__ __forceinline__ void fused_forward_hidden(FusedLds<H>& S, const float* __restrict__ params,
-                                                     const W16& w, const MlpOffsets& o, int d_in,
+                                                     const MlpOffsets& o, int d_in,
                                                      const float* __restrict__ X,
                                                      int x_rows, const int32_t* __restrict__ rows, int row0,
                                                      int nrows, const float* __restrict__ mu,
@@ -173,7 +174,7 @@ __device__ __forceinline__ void fused_forward_hidden(FusedLds<H>& S, const float
     for (int t = wave; t < 2 * (H / 16); t += kFWaves) {
         const int tm = t & 1, tn = t >> 1;
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        const bf16x8 b = PRE ? frag_g(w.w1, kFKin, 16 * tn, 0, lane) : frag_w(params + o.W1, d_in, H, d_in, 16 * tn, 0, lane);
+        const bf16x8 b = frag_w(params + o.W1, d_in, H, d_in, 16 * tn, 0, lane);
         acc = mfma(frag_lds(S.xs, kFKin + 8, 16 * tm, 0, lane), b, acc);
         const int n = 16 * tn + (lane & 15);
         const float bias = params[o.b1 + n];
@@ -193,7 +194,7 @@ __device__ __forceinline__ void fused_forward_hidden(FusedLds<H>& S, const float
 #pragma unroll
         for (int k0 = 0; k0 < H; k0 += 32)
             acc = mfma(frag_lds(S.h1, HS, 16 * tm, k0, lane),
-                       PRE ? frag_g(w.w2, H, 16 * tn, k0, lane) : frag_w(params + o.W2, H, H, H, 16 * tn, k0, lane), acc);
+                       frag_w(params + o.W2, H, H, H, 16 * tn, k0, lane), acc);
         const int n = 16 * tn + (lane & 15);
         const float bias = params[o.b2 + n];
 #pragma unroll
@@ -208,15 +209,15 @@ __device__ __forceinline__ void fused_forward_hidden(FusedLds<H>& S, const float
 }
 
 // Layer 3 of tile t: returns the float32 outputs (bias added).
-template <int H, bool PRE>
-__device__ __forceinline__ f32x4 fused_layer3(const FusedLds<H>& S, const float* __restrict__ params, const W16& w,
+template <int H>
+__device__ __forceinline__ f32x4 fused_layer3(const FusedLds<H>& S, const float* __restrict__ params,
                                               const MlpOffsets& o, int d_out, int tm, int tn, int lane) {
     constexpr int HS = FusedLds<H>::HS;
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int k0 = 0; k0 < H; k0 += 32)
         acc = mfma(frag_lds(S.h2, HS, 16 * tm, k0, lane),
-                   PRE ? frag_g(w.w3, H, 16 * tn, k0, lane) : frag_w(params + o.W3, H, d_out, H, 16 * tn, k0, lane), acc);
+                   frag_w(params + o.W3, H, d_out, H, 16 * tn, k0, lane), acc);
     const int n = 16 * tn + (lane & 15);
     const float bias = n < d_out ? params[o.b3 + n] : 0.f;
 #pragma unroll
@@ -233,13 +234,12 @@ k_mlp_predict(const float* __restrict__ params, int d_in, int d_out, const float
     const dvq_mlp_shape sh{d_in, H, d_out};
     const MlpOffsets o = offsets(sh);
     const int row0 = blockIdx.x * kFR, nrows = batch - row0 < kFR ? batch - row0 : kFR;
-    const W16 w{};
-    fused_forward_hidden<H, false>(S, params, w, o, d_in, X, batch, nullptr, row0, nrows, mu, isd);
+    fused_forward_hidden<H>(S, params, o, d_in, X, batch, nullptr, row0, nrows, mu, isd);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ntn = (d_out + 15) / 16;
     for (int t = wave; t < 2 * ntn; t += kFWaves) {
         const int tm = t & 1, tn = t >> 1;
-        const f32x4 y = fused_layer3<H, false>(S, params, w, o, d_out, tm, tn, lane);
+        const f32x4 y = fused_layer3<H>(S, params, o, d_out, tm, tn, lane);
         const int n = 16 * tn + (lane & 15);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -251,6 +251,18 @@ k_mlp_predict(const float* __restrict__ params, int d_in, int d_out, const float
 
 // One chunk's forward pass, loss and partial gradient (same packing as the
 // parameters) into pg[blockIdx.x][*]; its loss sum into lossp[blockIdx.x].
+// Wavefront w owns column tile w of every product whose output is H wide
+// (both 16-row halves of the chunk, so each weight fragment is loaded once)
+// and output tile (w mod 2, w / 2) when w < 2 ceil(d_out / 16).  The
+// weights of the step live in device memory and each phase ends at a
+// barrier (which waits for LDS traffic only), so each wavefront issues its
+// global loads one phase ahead of their use: the input and target rows and
+// the layer-1/2 fragments at the start, the layer-3 and W3^T fragments during
+// layer 2, the W2^T fragments during layer 3.  Loads complete in issue
+// order, hence the order of use; they are not all issued at the start
+// because the compute unit's memory pipeline serves them in turn, and the
+// bulk of the weights would then delay the input rows the first product
+// waits for.
 template <int H>
 __global__ void __launch_bounds__(kFThreads)
 k_mlp_train_chunk(const float* __restrict__ params, int d_in, int d_out, const float* __restrict__ X,
@@ -258,6 +270,9 @@ k_mlp_train_chunk(const float* __restrict__ params, int d_in, int d_out, const f
                   const float* __restrict__ mu, const float* __restrict__ isd, W16 w, float* __restrict__ pg,
                   double* __restrict__ lossp) {
     constexpr int HS = FusedLds<H>::HS;
+    constexpr int HT = H / 16, KH = H / 32, KDM = kFDmax / 32;
+    static_assert(HT <= kFWaves, "one hidden column tile per wavefront");
+    static_assert(2 * (kFDmax / 16) <= kFWaves, "one output tile per wavefront");
     extern __shared__ __align__(16) unsigned char smem[];
     FusedLds<H>& S = *reinterpret_cast<FusedLds<H>*>(smem);
     const dvq_mlp_shape sh{d_in, H, d_out};
@@ -265,80 +280,199 @@ k_mlp_train_chunk(const float* __restrict__ params, int d_in, int d_out, const f
     const int row0 = blockIdx.x * kFR, nrows = batch - row0 < kFR ? batch - row0 : kFR;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     float* g = pg + (int64_t)blockIdx.x * o.total;
-    fused_forward_hidden<H, true>(S, params, w, o, d_in, X, x_rows, rows, row0, nrows, mu, isd);
+    const int ntn = (d_out + 15) / 16, nkd = (d_out + 31) / 32;
+    const bool hcol = wave < HT, ytile = wave < 2 * ntn;
+    const int cn = 16 * wave + (lane & 15);  // the lane's column in its tiles
+    const int rq = 4 * (lane >> 4);          // its first row in a 16-row tile
+    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+    const bf16x8 zero8 = {};
 
-    // layer 3, loss and dY = sin(Y - T) / (batch * d_out); zeros past the batch
-    const int ntn = (d_out + 15) / 16;
-    const float inv = 1.0f / ((float)batch * (float)d_out);
-    double lsum = 0.0;
+    // Source rows: the thread's input row and, in the wavefronts of the
+    // output layer, the lane's four target rows (-1: none).  Every global
+    // load of the chunk depends on these or on nothing, so two round trips
+    // to device memory precede the first product.
+    static_assert(kFR * kFKin == kFThreads, "one input element per thread");
+    const int xr = tid / kFKin, xk = tid - xr * kFKin;
+    const int ytm = wave & 1, yn = 16 * (wave >> 1) + (lane & 15);  // output tile (ytm, wave / 2)
+    // (rows r >= nrows load row nrows - 1 and are then dropped, so the five
+    // loads are unconditional and in flight together)
+    int rr[5];
+    rr[0] = xr;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) rr[1 + i] = 16 * ytm + rq + i;
+    int64_t rv[5];
+    if (rows) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) rv[j] = rows[row0 + (rr[j] < nrows ? rr[j] : nrows - 1)];
+    } else {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) rv[j] = row0 + rr[j];
+    }
+#pragma unroll
+    for (int j = 0; j < 5; ++j) rv[j] = rr[j] < nrows && rv[j] >= 0 && rv[j] < x_rows ? rv[j] : -1;
+    const int64_t xsrc = rv[0];
+    // the standardised input element (zero past the batch and past d_in)
+    // and the targets (every lane loads, an in-bounds element where there is
+    // no target, so the loads are in flight together)
+    const bool xin = xsrc >= 0 && xk < d_in;
+    const int xkc = xk < d_in ? xk : 0;
+    const float xraw = X[(xin ? xsrc : 0) * d_in + xkc];
+    const float xmu = mu ? mu[xkc] : 0.f, xisd = mu ? isd[xkc] : 1.f;
+    float tv[4] = {0.f, 0.f, 0.f, 0.f};
+    int valid = 0;  // bit i: row 16 ytm + rq + i has a target in column yn
+    if (ytile) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const bool ok = rv[1 + i] >= 0 && yn < d_out;
+            tv[i] = T[(ok ? rv[1 + i] : 0) * d_out + (yn < d_out ? yn : 0)];
+            valid |= (int)ok << i;
+        }
+    }
+    // weights of layers 1 and 2 (hidden column tile), in the order of use
+    // (loads complete in order)
+    bf16x8 f1 = zero8, fa[KH], fb[KH], fc[KDM];
+    float bias1 = 0.f, bias2 = 0.f, bias3 = 0.f;
+#pragma unroll
+    for (int k = 0; k < KH; ++k) fa[k] = fb[k] = zero8;
+#pragma unroll
+    for (int k = 0; k < KDM; ++k) fc[k] = zero8;
+    if (hcol) {
+        bias1 = params[o.b1 + cn];
+        f1 = frag_g(w.w1, kFKin, 16 * wave, 0, lane);
+        bias2 = params[o.b2 + cn];
+#pragma unroll
+        for (int k = 0; k < KH; ++k) fa[k] = frag_g(w.w2, H, 16 * wave, 32 * k, lane);
+    }
+    {
+        const float xv = xin ? (mu ? (xraw - xmu) * xisd : xraw) : 0.f;
+        const __bf16 q = to_bf16(xv);
+        S.xs[xr * (kFKin + 8) + xk] = q;
+        S.xT[xk * kFRS + xr] = q;
+    }
+    // dY cleared (columns past d_out stay zero)
     for (int e = tid; e < kFR * kFDS; e += kFThreads) S.dy[e] = to_bf16(0.f);
     for (int e = tid; e < kFDmax * kFRS; e += kFThreads) S.dyT[e] = to_bf16(0.f);
     __syncthreads();
-    for (int t = wave; t < 2 * ntn; t += kFWaves) {
-        const int tm = t & 1, tn = t >> 1;
-        const f32x4 y = fused_layer3<H, true>(S, params, w, o, d_out, tm, tn, lane);
-        const int n = 16 * tn + (lane & 15);
-        f32x4 d = {0.f, 0.f, 0.f, 0.f};
+
+    // layer 1: [32 x 32] x W1^T, one contraction step per tile
+    if (hcol) {
+#pragma unroll
+        for (int tm = 0; tm < 2; ++tm) {
+            const f32x4 acc = mfma(frag_lds(S.xs, kFKin + 8, 16 * tm, 0, lane), f1, zero4);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * tm + rq + i;
+                const __bf16 q = to_bf16(fmaxf(acc[i] + bias1, 0.f));
+                S.h1[r * HS + cn] = q;
+                S.h1T[cn * kFRS + r] = q;
+            }
+        }
+    }
+    __syncthreads();
+
+    // layer 2: [32 x H] x W2^T
+    if (hcol) {
+#pragma unroll
+        for (int tm = 0; tm < 2; ++tm) {
+            f32x4 acc = zero4;
+#pragma unroll
+            for (int k = 0; k < KH; ++k) acc = mfma(frag_lds(S.h1, HS, 16 * tm, 32 * k, lane), fa[k], acc);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * tm + rq + i;
+                const __bf16 q = to_bf16(fmaxf(acc[i] + bias2, 0.f));
+                S.h2[r * HS + cn] = q;
+                S.h2T[cn * kFRS + r] = q;
+            }
+        }
+    }
+    // loads for layer 3 (output tile) and for dZ2 = dY W3 (W3^T)
+    if (ytile) {
+        bias3 = yn < d_out ? params[o.b3 + yn] : 0.f;
+#pragma unroll
+        for (int k = 0; k < KH; ++k) fb[k] = frag_g(w.w3, H, 16 * (wave >> 1), 32 * k, lane);
+    }
+    if (hcol) {
+#pragma unroll
+        for (int k = 0; k < KDM; ++k)
+            if (k < nkd) fc[k] = frag_g(w.w3t, kFDmax, 16 * wave, 32 * k, lane);
+    }
+    __syncthreads();
+
+    // layer 3, loss and dY = sin(Y - T) / (batch * d_out); zeros past the batch
+    const float inv = 1.0f / ((float)batch * (float)d_out);
+    double lsum = 0.0;
+    if (ytile) {
+        f32x4 acc = zero4;
+#pragma unroll
+        for (int k = 0; k < KH; ++k) acc = mfma(frag_lds(S.h2, HS, 16 * ytm, 32 * k, lane), fb[k], acc);
+        f32x4 d = zero4;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int r = 16 * tm + 4 * (lane >> 4) + i;
-            const int64_t src = r < nrows ? (rows ? (int64_t)rows[row0 + r] : (int64_t)(row0 + r)) : -1;
-            if (src >= 0 && src < x_rows && n < d_out) {
-                const float diff = y[i] - T[src * d_out + n];
-                d[i] = sinf(diff) * inv;
-                lsum += 1.0 - cos((double)diff);
+            const int r = 16 * ytm + rq + i;
+            if (valid & (1 << i)) {
+                // sin(x) = 2 sin(x/2) cos(x/2) and 1 - cos(x) = 2 sin(x/2)^2
+                // from one float sincos (the loss term without the
+                // cancellation of 1 - cos near x = 0)
+                const float diff = (acc[i] + bias3) - tv[i];
+                float sh, ch;
+                sincosf(0.5f * diff, &sh, &ch);
+                d[i] = 2.f * sh * ch * inv;
+                lsum += 2.0 * (double)sh * (double)sh;
             }
             const __bf16 q = to_bf16(d[i]);
-            S.dy[r * kFDS + n] = q;
-            S.dyT[n * kFRS + r] = q;
+            S.dy[r * kFDS + yn] = q;
+            S.dyT[yn * kFRS + r] = q;
         }
         const float cs = tile_colsum(d);
-        if (lane < 16) S.colsum[tm][n] = cs;
+        if (lane < 16) S.colsum[ytm][yn] = cs;
+    }
+    // loads for dZ1 = dZ2 W2 (W2^T fragments, over the layer-2 ones)
+    if (hcol) {
+#pragma unroll
+        for (int k = 0; k < KH; ++k) fa[k] = frag_g(w.w2t, H, 16 * wave, 32 * k, lane);
     }
     lsum = wave_sum(lsum);
     if (lane == 0) S.loss[wave] = lsum;
     __syncthreads();
     if (tid == 0) {
         double ls = 0.0;
-        for (int w = 0; w < kFWaves; ++w) ls += S.loss[w];
+        for (int v = 0; v < kFWaves; ++v) ls += S.loss[v];
         lossp[blockIdx.x] = ls;
     }
     for (int n = tid; n < d_out; n += kFThreads) g[o.b3 + n] = S.colsum[0][n] + S.colsum[1][n];
 
     // dZ2 = (dY W3) * [h2 > 0] (written over h2, each element read and
     // written by the lane that owns it, and as dz2T; column sums for b2 into
-    // cs2), beside dW3 = dY^T h2 (contraction over the chunk's rows: one
-    // step); the longer dZ2 tiles come first
-    const int kd = (d_out + 31) / 32 * 32;
-    const int tz = 2 * (H / 16);
-    for (int t = wave; t < tz + ntn * (H / 16); t += kFWaves) {
-        if (t < tz) {
-            const int tm = t & 1, tn = t >> 1;
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-            for (int k0 = 0; k0 < kd; k0 += 32)
-                acc = mfma(frag_lds(S.dy, kFDS, 16 * tm, k0, lane), frag_g(w.w3t, kFDmax, 16 * tn, k0, lane), acc);
-            const int n = 16 * tn + (lane & 15);
+    // cs2), beside dW3 = dY^T h2 (contraction over the chunk's rows: one step)
+    if (hcol) {
+#pragma unroll
+        for (int tm = 0; tm < 2; ++tm) {
+            f32x4 acc = zero4;
+#pragma unroll
+            for (int k = 0; k < KDM; ++k)
+                if (k < nkd) acc = mfma(frag_lds(S.dy, kFDS, 16 * tm, 32 * k, lane), fc[k], acc);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int r = 16 * tm + 4 * (lane >> 4) + i;
-                const bool on = (float)S.h2[r * HS + n] > 0.f;
+                const int r = 16 * tm + rq + i;
+                const bool on = (float)S.h2[r * HS + cn] > 0.f;
                 acc[i] = on ? acc[i] : 0.f;
                 const __bf16 q = to_bf16(acc[i]);
-                S.h2[r * HS + n] = q;
-                S.dz2T[n * kFRS + r] = q;
+                S.h2[r * HS + cn] = q;
+                S.dz2T[cn * kFRS + r] = q;
             }
             const float cs = tile_colsum(acc);
-            if (lane < 16) S.cs2[tm][n] = cs;
-        } else {
-            const int u = t - tz, tm = u % ntn, tn = u / ntn;  // tm over d_out, tn over H
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-            acc = mfma(frag_lds(S.dyT, kFRS, 16 * tm, 0, lane), frag_lds(S.h2T, kFRS, 16 * tn, 0, lane), acc);
-            const int n = 16 * tn + (lane & 15);
+            if (lane < 16) S.cs2[tm][cn] = cs;
+        }
+    }
+    for (int u = wave; u < ntn * HT; u += kFWaves) {
+        const int tm = u % ntn, tn = u / ntn;  // tm over d_out, tn over H
+        const f32x4 acc = mfma(frag_lds(S.dyT, kFRS, 16 * tm, 0, lane), frag_lds(S.h2T, kFRS, 16 * tn, 0, lane), zero4);
+        const int n = 16 * tn + (lane & 15);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int d = 16 * tm + 4 * (lane >> 4) + i;
-                if (d < d_out) g[o.W3 + (int64_t)d * H + n] = acc[i];
-            }
+        for (int i = 0; i < 4; ++i) {
+            const int d = 16 * tm + rq + i;
+            if (d < d_out) g[o.W3 + (int64_t)d * H + n] = acc[i];
         }
     }
     __syncthreads();
@@ -346,45 +480,42 @@ k_mlp_train_chunk(const float* __restrict__ params, int d_in, int d_out, const f
 
     // dZ1 = (dZ2 W2) * [h1 > 0] as dZ1^T over h2T (h2T was last read by dW3;
     // column sums for b1 into colsum), beside dW2 = dZ2^T h1
-    for (int t = wave; t < tz + (H / 16) * (H / 16); t += kFWaves) {
-        if (t < tz) {
-            const int tm = t & 1, tn = t >> 1;
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    if (hcol) {
 #pragma unroll
-            for (int k0 = 0; k0 < H; k0 += 32)
-                acc = mfma(frag_lds(S.h2, HS, 16 * tm, k0, lane), frag_g(w.w2t, H, 16 * tn, k0, lane), acc);
-            const int n = 16 * tn + (lane & 15);
+        for (int tm = 0; tm < 2; ++tm) {
+            f32x4 acc = zero4;
+#pragma unroll
+            for (int k = 0; k < KH; ++k) acc = mfma(frag_lds(S.h2, HS, 16 * tm, 32 * k, lane), fa[k], acc);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int r = 16 * tm + 4 * (lane >> 4) + i;
-                const bool on = (float)S.h1[r * HS + n] > 0.f;
+                const int r = 16 * tm + rq + i;
+                const bool on = (float)S.h1[r * HS + cn] > 0.f;
                 acc[i] = on ? acc[i] : 0.f;
-                S.h2T[n * kFRS + r] = to_bf16(acc[i]);
+                S.h2T[cn * kFRS + r] = to_bf16(acc[i]);
             }
             const float cs = tile_colsum(acc);
-            if (lane < 16) S.colsum[tm][n] = cs;
-        } else {
-            const int u = t - tz, tm = u % (H / 16), tn = u / (H / 16);
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-            acc = mfma(frag_lds(S.dz2T, kFRS, 16 * tm, 0, lane), frag_lds(S.h1T, kFRS, 16 * tn, 0, lane), acc);
-            const int n = 16 * tn + (lane & 15);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) g[o.W2 + (int64_t)(16 * tm + 4 * (lane >> 4) + i) * H + n] = acc[i];
+            if (lane < 16) S.colsum[tm][cn] = cs;
         }
+    }
+    for (int u = wave; u < HT * HT; u += kFWaves) {
+        const int tm = u % HT, tn = u / HT;
+        const f32x4 acc = mfma(frag_lds(S.dz2T, kFRS, 16 * tm, 0, lane), frag_lds(S.h1T, kFRS, 16 * tn, 0, lane), zero4);
+        const int n = 16 * tn + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) g[o.W2 + (int64_t)(16 * tm + rq + i) * H + n] = acc[i];
     }
     __syncthreads();
     for (int n = tid; n < H; n += kFThreads) g[o.b1 + n] = S.colsum[0][n] + S.colsum[1][n];
 
     // dW1 = dZ1^T X
     const int nti = (d_in + 15) / 16;
-    for (int t = wave; t < (H / 16) * nti; t += kFWaves) {
-        const int tm = t % (H / 16), tn = t / (H / 16);
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mfma(frag_lds(S.h2T, kFRS, 16 * tm, 0, lane), frag_lds(S.xT, kFRS, 16 * tn, 0, lane), acc);
+    for (int t = wave; t < HT * nti; t += kFWaves) {
+        const int tm = t % HT, tn = t / HT;
+        const f32x4 acc = mfma(frag_lds(S.h2T, kFRS, 16 * tm, 0, lane), frag_lds(S.xT, kFRS, 16 * tn, 0, lane), zero4);
         const int n = 16 * tn + (lane & 15);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-            if (n < d_in) g[o.W1 + (int64_t)(16 * tm + 4 * (lane >> 4) + i) * d_in + n] = acc[i];
+            if (n < d_in) g[o.W1 + (int64_t)(16 * tm + rq + i) * d_in + n] = acc[i];
     }
 }
 
