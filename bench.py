@@ -58,12 +58,12 @@ CSRC = os.path.join(ROOT, "paper_2604_14435_amd", "csrc")
 MEASURED_TRAFFIC = {
     "k_terms_fast<float,10,cz,plus>": {
         "sources": ["circuits_fast.hip", "wave_state.h", "circuits.h", "common.h"],
-        "sources_sha256": "ca1ab50b6fb086ea", "fetch_kib": 182.5, "write_kib": 704.0},
+        "sources_sha256": "b879ffb65299cf95", "fetch_kib": 182.5, "write_kib": 704.0},
     "k_fwht_fused<6,2> (n=12 dense)": {
         "sources": ["decompose.hip", "common.h"],
-        "sources_sha256": "6f82fc5f8a9e75fe", "fetch_kib": 66032.6, "write_kib": 262229.7},
+        "sources_sha256": "6f82fc5f8a9e75fe", "fetch_kib": 66026.6, "write_kib": 262221.9},
 }
-FETCH_SCALE, WRITE_SCALE = 262144.0 / 131092.7, 1.0
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131093.2, 1.0
 
 
 def sources_sha256(names) -> str:
@@ -1216,7 +1216,11 @@ def main() -> int:
     # the same steps launched eagerly, with HIP events around every circuit
     # kernel: the roofline's kernel time
     gc.collect()  # the graphs' teardown stays out of the timed steps
-    torch.cuda.synchronize()
+    t_warm = time.perf_counter()  # and the GPU clock up again after the pause
+    while time.perf_counter() - t_warm < 0.2:
+        for _ in range(50):
+            fast_step(theta, False)
+        torch.cuda.synchronize()
     t0 = time.perf_counter()
     marks = [t0]
     for _ in range(args.steps):

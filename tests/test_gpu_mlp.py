@@ -184,7 +184,7 @@ def test_fused_predict_matches_oracle(d_in, h, d_out, B):
     _close(Y.cpu().numpy(), y)
 
 
-@pytest.mark.parametrize("d_in,h,d_out,B", [(2, 256, 40, 256), (2, 256, 80, 70), (3, 64, 12, 37)])
+@pytest.mark.parametrize("d_in,h,d_out,B", [(2, 256, 40, 256), (2, 256, 80, 70), (3, 64, 12, 37), (4, 128, 128, 33)])
 def test_fused_train_step_matches_oracle(d_in, h, d_out, B):
     """One fused step on a minibatch chosen by a row-index array: loss,
     gradient (packed) and the AdamW update against the oracle's forward,
@@ -248,6 +248,29 @@ def test_fused_train_step_ignores_rows_outside_x():
         outs.append((params.clone(), g.clone()))
     for p_, g_ in outs[1:]:
         assert torch.equal(p_, outs[0][0]) and torch.equal(g_, outs[0][1])
+
+
+@pytest.mark.parametrize("B", [1, 33, 256])
+def test_fused_train_step_without_rows_equals_identity_rows(B):
+    """With no row-index array the step takes the first `batch` rows of X
+    and T: bit-equal to the same step given rows 0..batch-1 (every row of a
+    chunk present, a ragged last chunk, a single row)."""
+    rng = np.random.default_rng(B)
+    d_in, h, d_out, S = 2, 256, 40, 300
+    shape = api.mlp_shape(d_in, h, d_out)
+    X = torch.from_numpy(rng.standard_normal((S, d_in)).astype(np.float32)).to(DEV)
+    T = torch.from_numpy(rng.uniform(-2, 2, (S, d_out)).astype(np.float32)).to(DEV)
+    base = torch.from_numpy(_pack(om.init_params(d_in, h, d_out, seed=2))).to(DEV)
+    stats = api.feature_stats(X)
+    outs = []
+    for rows in (None, torch.arange(B, dtype=torch.int32, device=DEV)):
+        params, m, v = base.clone(), torch.zeros_like(base), torch.zeros_like(base)
+        g = torch.empty_like(base)
+        loss = torch.empty(1, dtype=torch.float64, device=DEV)
+        api.mlp_train_step(shape, params, m, v, 1, X, T, rows=rows, batch=B, stats=stats, grads=g, loss=loss)
+        outs.append((params, g, loss))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    assert outs[0][2].item() == outs[1][2].item()
 
 
 def test_race_starts_keeps_the_better_run():
