@@ -342,32 +342,90 @@ __device__ __forceinline__ void store_half0(const T* re, const T* im, cplx<T>* S
 // coefficient once per string, and a per-i part that is uniform over the
 // wavefront; the gather address is a per-lane base plus 66 (i ^ (x >> 6)),
 // also uniform.  The W wavefronts of a row take disjoint blocks of i.
+// The strings and coefficients come from device memory, 64 per vector load
+// (one per lane) and then one string at a time out of the registers
+// (v_readlane), and the gathers of eight strings are issued together before
+// their products; read one string at a time from LDS, each string paid a
+// round trip for itself and one for its gathers.  Every output element
+// still accumulates the strings in order, one string after the other.
 // With FRAME, out[k] receives the sum at index pi(k) (the ladder frame):
 // sum index m is written to slot pi^-1(m).
 template <typename T, int NQ, int W, bool FRAME = false>
-__device__ __forceinline__ void wave_pauli_sum(cplx<T>* out, const cplx<T>* in, const dvq_pauli* sp,
-                                               const dvq_c128* cp, int L, bool conj_c, int lane, int wave) {
-    constexpr int KPL = (1 << NQ) / 64, KW = KPL / W;
+__device__ __forceinline__ void wave_pauli_sum(cplx<T>* out, const cplx<T>* in, const dvq_pauli* __restrict__ sp,
+                                               const dvq_c128* __restrict__ cp, int L, bool conj_c, int lane,
+                                               int wave) {
+    constexpr int KPL = (1 << NQ) / 64, KW = KPL / W, U = 8;
     static_assert(KW * W == KPL, "blocks per wavefront");
-    const int i0 = wave * KW;
+    const int i0 = __builtin_amdgcn_readfirstlane(wave * KW);  // uniform: the gather offsets are scalars
     T ar[KW], ai[KW];
 #pragma unroll
     for (int i = 0; i < KW; ++i) ar[i] = ai[i] = (T)0;
-    for (int l = 0; l < L; ++l) {
-        const uint32_t x = __builtin_amdgcn_readfirstlane(sp[l].x), z = __builtin_amdgcn_readfirstlane(sp[l].z);
-        cplx<T> c = {(T)cp[l].re, conj_c ? -(T)cp[l].im : (T)cp[l].im};
-        c = mul_ipow(c, (int)__popc(x & z) + 2 * parity(z & x) + 2 * parity(z & (uint32_t)lane));
+    // string l (x, z, coefficient loaded): its coefficient with the lane's
+    // phase (the uniform power of i, then the lane's sign) and its KW gathers
+    auto fetch = [&](uint32_t x, uint32_t z, double cre, double cim, cplx<T>& c, int& zh, cplx<T>* v) {
+        // (a + ib) i^p as swaps and sign changes on uniform values (scalar
+        // selects instead of a branch per string): p = 1 (-b, a), 2 (-a, -b),
+        // 3 (b, -a)
+        const int p = (int)__popc(x & z) + 2 * parity(z & x);
+        const double a = cre, b = conj_c ? -cim : cim;
+        double r = (p & 1) ? b : a, m = (p & 1) ? a : b;
+        if (((p + 1) >> 1) & 1) r = -r;
+        if (p & 2) m = -m;
+        c = {(T)r, (T)m};
+        if (parity(z & (uint32_t)lane)) c = {-c.re, -c.im};
         const int bl = lane ^ (int)(x & 63u);
         const cplx<T>* src = in + (bl + (bl >> 5));
-        const int xh = (int)(x >> 6), zh = (int)(z >> 6);
+        const int xh = (int)(x >> 6);
+        zh = (int)(z >> 6);
+#pragma unroll
+        for (int i = 0; i < KW; ++i) v[i] = src[66 * ((i0 + i) ^ xh)];
+    };
+    auto accumulate = [&](const cplx<T>& c, int zh, const cplx<T>* v) {
 #pragma unroll
         for (int i = 0; i < KW; ++i) {
-            const int ii = i0 + i;
-            const cplx<T> v = src[66 * (ii ^ xh)];
-            const bool neg = parity((uint32_t)(zh & ii));
+            const bool neg = parity((uint32_t)(zh & (i0 + i)));
             const T cr = neg ? -c.re : c.re, ci = neg ? -c.im : c.im;
-            ar[i] = fmat(cr, v.re, fmat(-ci, v.im, ar[i]));
-            ai[i] = fmat(cr, v.im, fmat(ci, v.re, ai[i]));
+            ar[i] = fmat(cr, v[i].re, fmat(-ci, v[i].im, ar[i]));
+            ai[i] = fmat(cr, v[i].im, fmat(ci, v[i].re, ai[i]));
+        }
+    };
+    // Strings are taken 64 at a time: lane j loads string base + j (one
+    // vector load each, one wait per 64 strings) and the sum reads them back
+    // with v_readlane, so no memory wait sits between two strings.
+    for (int base = 0; base < L; base += 64) {
+        const int nb = L - base < 64 ? L - base : 64;
+        const int j = lane < nb ? base + lane : base;
+        const uint32_t lx = sp[j].x, lz = sp[j].z;
+        const uint64_t lre = __builtin_bit_cast(uint64_t, cp[j].re), lim = __builtin_bit_cast(uint64_t, cp[j].im);
+        auto take = [&](int k, uint32_t& x, uint32_t& z, double& cre, double& cim) {
+            x = (uint32_t)__builtin_amdgcn_readlane((int)lx, k);
+            z = (uint32_t)__builtin_amdgcn_readlane((int)lz, k);
+            cre = __builtin_bit_cast(double, ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(lre >> 32), k) << 32) |
+                                                 (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)lre, k));
+            cim = __builtin_bit_cast(double, ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(lim >> 32), k) << 32) |
+                                                 (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)lim, k));
+        };
+        int k = 0;
+        for (; k + U <= nb; k += U) {
+            uint32_t x[U], z[U];
+            double cre[U], cim[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) take(k + u, x[u], z[u], cre[u], cim[u]);
+            cplx<T> c[U], v[U][KW];
+            int zh[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) fetch(x[u], z[u], cre[u], cim[u], c[u], zh[u], v[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u) accumulate(c[u], zh[u], v[u]);
+        }
+        for (; k < nb; ++k) {
+            uint32_t x, z;
+            double cre, cim;
+            take(k, x, z, cre, cim);
+            cplx<T> c, v[KW];
+            int zh;
+            fetch(x, z, cre, cim, c, zh, v);
+            accumulate(c, zh, v);
         }
     }
     if constexpr (FRAME) {
@@ -421,7 +479,6 @@ __host__ __device__ constexpr size_t wave_adjoint_lds(int layers, int L) {
     return (size_t)(2 * N + (2 * N) / 32) * sizeof(cplx<T>)      // scratch for layout swaps
            + regions * (size_t)(N + N / 32) * sizeof(cplx<T>)
            + (size_t)NQ * 33 * sizeof(double)                    // gradient partials
-           + (size_t)L * (sizeof(dvq_pauli) + sizeof(dvq_c128))  // strings, coeffs
            + (size_t)2 * NQ * layers * sizeof(T);                // rotation table
 }
 
@@ -442,9 +499,7 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
     constexpr bool CNOT = ENT == DVQ_ENT_CNOT_LADDER;
     cplx<T>* RXF = RV + N1;  // x in the ladder frame (CNOT ladder only)
     double* gb = reinterpret_cast<double*>(CNOT ? RXF + N1 : RV + N1);  // gradient partials [NQ][33]
-    dvq_pauli* sp = reinterpret_cast<dvq_pauli*>(gb + NQ * 33);
-    dvq_c128* cp = reinterpret_cast<dvq_c128*>(sp + L);
-    T* trig = reinterpret_cast<T*>(cp + L);
+    T* trig = reinterpret_cast<T*>(gb + NQ * 33);
     // W wavefronts per row: each runs the register phases redundantly (same
     // values written to the same LDS slots, every hand-over fenced by a
     // barrier) and takes 1/W of the Pauli sums; wavefront 0 writes the results.
@@ -452,10 +507,8 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
     const int64_t row = blockIdx.x;
     const int P = NQ * layers;
     const int64_t sys = per_row_system ? row * L : 0;
-    for (int l = threadIdx.x; l < L; l += 64 * W) {
-        sp[l] = strings[sys + l];
-        cp[l] = coeffs[sys + l];
-    }
+    const dvq_pauli* __restrict__ sp = strings + sys;
+    const dvq_c128* __restrict__ cp = coeffs + sys;
     rotation_table<T>(theta + row * P, P, trig, lane);  // ends with a barrier
 
     // forward: both halves start in |0> and evolve identically
