@@ -551,28 +551,34 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
     if (kind == DVQ_COST_LOCAL) {
         double aE, aPsi;
         if (bkind == DVQ_B_PLUS) {
-            // u = H^n y in registers (LO -> HI), E, D u, H^n again (HI -> LO)
-            load_halves<T, NQ, false>(re, im, RY, RY, lane, 0);
-            h_range<T, NQ, false, 0, NQ>(re, im);
-            relayout<T, NQ, false>(re, im, S, lane);
-            h_range<T, NQ, true, Lay<NQ, false>::RB, NQ>(re, im);
+            // U_b = H^n and H Z_j H = X_j: E = <y|H^n D H^n|y> = sum_j <y|X_j|y>
+            // and H^n D H^n y = sum_j X_j y (D = sum_j Z_j), n bit-flip
+            // gathers per amplitude with the amplitudes split between the W
+            // wavefronts (E summed in float64 from the products)
+            constexpr int KW = (N / 64) / W;
             double es = 0.0;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int g = Lay<NQ, true>::g(lane, r);
-                const T d = (T)(NQ - 2 * (int)__popc((unsigned)(g & (N - 1))));
-                if (!(lane & 32)) es += ((double)re[r] * re[r] + (double)im[r] * im[r]) * (double)d;
-                re[r] *= d;
-                im[r] *= d;
+            for (int i = 0; i < KW; ++i) {
+                const int k = lane + 64 * (wave * KW + i);
+                const cplx<T> yk = RY[pad_slot(k)];
+                T sr = (T)0, si = (T)0;
+#pragma unroll
+                for (int j = 0; j < NQ; ++j) {
+                    const cplx<T> yj = RY[pad_slot(k ^ (1 << j))];
+                    sr += yj.re;
+                    si += yj.im;
+                    es += (double)yk.re * yj.re + (double)yk.im * yj.im;
+                }
+                RV[pad_slot(k)] = {sr, si};
             }
-            const double E = wave_sum(es);
+            es = wave_sum(es);
+            if (lane == 0) gb[wave] = es;  // gb holds the gradient partials only from the reverse sweep on
+            __syncthreads();
+            double E = 0.0;
+            for (int v = 0; v < W; ++v) E += gb[v];
             cost = 0.5 - 0.5 * E / (NQ * Psi);
             aE = -0.5 / (NQ * Psi);
             aPsi = 0.5 * E / (NQ * Psi * Psi);
-            h_range<T, NQ, true, Lay<NQ, false>::RB, NQ>(re, im);
-            relayout<T, NQ, true>(re, im, S, lane);
-            h_range<T, NQ, false, 0, NQ>(re, im);
-            store_half0<T, NQ, false>(re, im, RV, lane, 0);
         } else {
             for (int k = lane; k < N; k += 64) RV[pad_slot(k)] = RY[pad_slot(k)];
             __syncthreads();

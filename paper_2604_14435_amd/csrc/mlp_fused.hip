@@ -4,7 +4,9 @@
 // Same arithmetic as the GEMM-per-layer path of mlp.hip: every GEMM operand
 // rounded to bfloat16, float32 accumulation on the matrix cores
 // (v_mfma_f32_16x16x32_bf16), bias, ReLU, ReLU masks and the bias gradients
-// in float32 on the unrounded values.
+// in float32 on the unrounded values; the loss term and its output gradient
+// come from one float sincos of half the difference (the same quantities to
+// float rounding).
 //
 // Layout.  A workgroup (16 wavefronts) owns a chunk of 32 batch rows and
 // keeps that chunk's activations in LDS as bfloat16, row-major where they

@@ -248,6 +248,24 @@ def test_register_adjoint_cnot_bench_system(layers):
             assert np.max(np.abs(g[0].cpu().numpy() - g0)) < tol_g, (kind, precision)
 
 
+@pytest.mark.parametrize("ent,precision", [("cz", "f64"), ("cnot", "f32"), ("cnot", "f64")])
+def test_register_adjoint_strings_beyond_one_block(ent, precision):
+    """L = 100 at n = 10: the Pauli sums take strings 64 at a time and eight
+    per batch, so this runs one full block, a second block of 36 and a
+    remainder of 4; vs the exact shift rule, local and global cost."""
+    n, layers = 10, 2
+    A, At, c, xs, zs, strings = _system(n, 1.0, -0.4, top_L=100)
+    th = theta_uniform(n * layers, seed=5)
+    an = api.AnsatzSpec(n, layers, ent)
+    tol_c, tol_g = (1e-12, 1e-10) if precision == "f64" else (1e-6, 1e-5)
+    for kind in ("local", "global"):
+        parts = lambda t: oc.parts_theta_dense(t, At, n, layers, ent, kind)
+        C0, g0 = oc.grad_parameter_shift(parts, th, n, kind)
+        C, g = api.vqls_grad_adjoint(an, _gpu(th), _gpu(c), _gpu(strings), kind, precision)
+        assert abs(C.item() - C0) < tol_c, kind
+        assert np.max(np.abs(g[0].cpu().numpy() - g0)) < tol_g, kind
+
+
 @pytest.mark.parametrize("ent,precision,b_kind", [("cz", "f64", "plus"), ("cnot", "f32", "vector"),
                                                   ("cnot", "f64", "plus")])
 def test_register_adjoint_rows_independent_of_batch(ent, precision, b_kind):
