@@ -341,31 +341,36 @@ __device__ __forceinline__ void store_half0(const T* re, const T* im, cplx<T>* S
 // k = lane + 64 i the last sign splits into a per-lane part, folded into the
 // coefficient once per string, and a per-i part that is uniform over the
 // wavefront; the gather address is a per-lane base plus 66 (i ^ (x >> 6)),
-// also uniform.  The W wavefronts of a row take disjoint blocks of i.
-// The strings and coefficients come from device memory, 64 per vector load
-// (one per lane) and then one string at a time out of the registers
-// (v_readlane), and the gathers of eight strings are issued together before
-// their products; read one string at a time from LDS, each string paid a
-// round trip for itself and one for its gathers.  Every output element
-// still accumulates the strings in order, one string after the other.
-// With FRAME, out[k] receives the sum at index pi(k) (the ladder frame):
-// sum index m is written to slot pi^-1(m).
+// also uniform.
+// The W = 4 wavefronts of a row take a quarter of the strings each, for
+// every amplitude (a string's own work -- its phase, its uniform offsets --
+// is paid by one wavefront, not by all four), into register partial sums;
+// the first three write theirs to p0, p1, p2 and the fourth adds them to its
+// own, in that order, and writes out.  p0 may be out itself when FRAME is
+// off (the fourth wavefront reads and writes the same slot); with FRAME,
+// out[k] receives the sum at index pi(k) (the ladder frame: sum index m is
+// written to slot pi^-1(m)) and none of p0..p2 may be out.
+// A wavefront's strings come from device memory, 64 per vector load (one per
+// lane), then one at a time out of the registers (v_readlane); the gathers
+// of two strings (n = 10) are issued together before their products.
 template <typename T, int NQ, int W, bool FRAME = false>
-__device__ __forceinline__ void wave_pauli_sum(cplx<T>* out, const cplx<T>* in, const dvq_pauli* __restrict__ sp,
+__device__ __forceinline__ void wave_pauli_sum(cplx<T>* out, const cplx<T>* in, cplx<T>* p0, cplx<T>* p1,
+                                               cplx<T>* p2, const dvq_pauli* __restrict__ sp,
                                                const dvq_c128* __restrict__ cp, int L, bool conj_c, int lane,
                                                int wave) {
-    constexpr int KPL = (1 << NQ) / 64, KW = KPL / W, U = 8;
-    static_assert(KW * W == KPL, "blocks per wavefront");
-    const int i0 = __builtin_amdgcn_readfirstlane(wave * KW);  // uniform: the gather offsets are scalars
-    T ar[KW], ai[KW];
+    static_assert(W == 4, "three partial regions and the last wavefront's registers");
+    constexpr int KPL = (1 << NQ) / 64, U = KPL <= 16 ? 2 : 1;  // n = 11: one string at a time (registers)
+    const int per = (L + W - 1) / W;
+    const int l0 = __builtin_amdgcn_readfirstlane(wave * per < L ? wave * per : L);
+    const int l1 = l0 + per < L ? l0 + per : L;
+    T ar[KPL], ai[KPL];
 #pragma unroll
-    for (int i = 0; i < KW; ++i) ar[i] = ai[i] = (T)0;
-    // string l (x, z, coefficient loaded): its coefficient with the lane's
-    // phase (the uniform power of i, then the lane's sign) and its KW gathers
+    for (int i = 0; i < KPL; ++i) ar[i] = ai[i] = (T)0;
+    // string (x, z, coefficient): its coefficient with the lane's phase (the
+    // uniform power of i by scalar selects, then the lane's sign) and its KPL
+    // gathers
     auto fetch = [&](uint32_t x, uint32_t z, double cre, double cim, cplx<T>& c, int& zh, cplx<T>* v) {
-        // (a + ib) i^p as swaps and sign changes on uniform values (scalar
-        // selects instead of a branch per string): p = 1 (-b, a), 2 (-a, -b),
-        // 3 (b, -a)
+        // (a + ib) i^p: p = 1 (-b, a), 2 (-a, -b), 3 (b, -a)
         const int p = (int)__popc(x & z) + 2 * parity(z & x);
         const double a = cre, b = conj_c ? -cim : cim;
         double r = (p & 1) ? b : a, m = (p & 1) ? a : b;
@@ -378,22 +383,19 @@ __device__ __forceinline__ void wave_pauli_sum(cplx<T>* out, const cplx<T>* in, 
         const int xh = (int)(x >> 6);
         zh = (int)(z >> 6);
 #pragma unroll
-        for (int i = 0; i < KW; ++i) v[i] = src[66 * ((i0 + i) ^ xh)];
+        for (int i = 0; i < KPL; ++i) v[i] = src[66 * (i ^ xh)];
     };
     auto accumulate = [&](const cplx<T>& c, int zh, const cplx<T>* v) {
 #pragma unroll
-        for (int i = 0; i < KW; ++i) {
-            const bool neg = parity((uint32_t)(zh & (i0 + i)));
+        for (int i = 0; i < KPL; ++i) {
+            const bool neg = parity((uint32_t)(zh & i));
             const T cr = neg ? -c.re : c.re, ci = neg ? -c.im : c.im;
             ar[i] = fmat(cr, v[i].re, fmat(-ci, v[i].im, ar[i]));
             ai[i] = fmat(cr, v[i].im, fmat(ci, v[i].re, ai[i]));
         }
     };
-    // Strings are taken 64 at a time: lane j loads string base + j (one
-    // vector load each, one wait per 64 strings) and the sum reads them back
-    // with v_readlane, so no memory wait sits between two strings.
-    for (int base = 0; base < L; base += 64) {
-        const int nb = L - base < 64 ? L - base : 64;
+    for (int base = l0; base < l1; base += 64) {
+        const int nb = l1 - base < 64 ? l1 - base : 64;
         const int j = lane < nb ? base + lane : base;
         const uint32_t lx = sp[j].x, lz = sp[j].z;
         const uint64_t lre = __builtin_bit_cast(uint64_t, cp[j].re), lim = __builtin_bit_cast(uint64_t, cp[j].im);
@@ -411,7 +413,7 @@ __device__ __forceinline__ void wave_pauli_sum(cplx<T>* out, const cplx<T>* in, 
             double cre[U], cim[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) take(k + u, x[u], z[u], cre[u], cim[u]);
-            cplx<T> c[U], v[U][KW];
+            cplx<T> c[U], v[U][KPL];
             int zh[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) fetch(x[u], z[u], cre[u], cim[u], c[u], zh[u], v[u]);
@@ -422,19 +424,30 @@ __device__ __forceinline__ void wave_pauli_sum(cplx<T>* out, const cplx<T>* in, 
             uint32_t x, z;
             double cre, cim;
             take(k, x, z, cre, cim);
-            cplx<T> c, v[KW];
+            cplx<T> c, v[KPL];
             int zh;
             fetch(x, z, cre, cim, c, zh, v);
             accumulate(c, zh, v);
         }
     }
-    if constexpr (FRAME) {
-        const int ul = ladder_unperm<NQ>(lane);
+    if (wave < W - 1) {
+        cplx<T>* pw = wave == 0 ? p0 : (wave == 1 ? p1 : p2);
 #pragma unroll
-        for (int i = 0; i < KW; ++i) out[pad_slot(ul ^ ladder_unperm<NQ>(64 * (i0 + i)))] = {ar[i], ai[i]};
-    } else {
+        for (int i = 0; i < KPL; ++i) pw[pad_slot(lane + 64 * i)] = {ar[i], ai[i]};
+    }
+    __syncthreads();
+    if (wave == W - 1) {
+        const int ul = FRAME ? ladder_unperm<NQ>(lane) : 0;
 #pragma unroll
-        for (int i = 0; i < KW; ++i) out[pad_slot(lane + 64 * (i0 + i))] = {ar[i], ai[i]};
+        for (int i = 0; i < KPL; ++i) {
+            const int k = pad_slot(lane + 64 * i);
+            const cplx<T> a = p0[k], b = p1[k], c = p2[k];
+            const cplx<T> sum = {((a.re + b.re) + c.re) + ar[i], ((a.im + b.im) + c.im) + ai[i]};
+            if constexpr (FRAME)
+                out[pad_slot(ul ^ ladder_unperm<NQ>(64 * i))] = sum;
+            else
+                out[k] = sum;
+        }
     }
     __syncthreads();
 }
@@ -539,7 +552,7 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
     }
 
     // y = A x, Psi = <y|y>
-    wave_pauli_sum<T, NQ, W>(RY, RX, sp, cp, L, false, lane, wave);
+    wave_pauli_sum<T, NQ, W>(RY, RX, RY, RV, S, sp, cp, L, false, lane, wave);  // RV, S free until later
     double ps = 0.0;
     for (int k = lane; k < N; k += 64) {
         const cplx<T> a = RY[pad_slot(k)];
@@ -639,7 +652,10 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
         __syncthreads();
     }
     // lambda = A^dag v -> RY (in the ladder frame for the CNOT ladder)
-    wave_pauli_sum<T, NQ, W, CNOT>(RY, RV, sp, cp, L, true, lane, wave);
+    // partials: y (RY) and the swap scratch S are dead; with the ladder frame
+    // the output is permuted, so the first partial goes to RX (the reverse
+    // sweep reads x from RXF)
+    wave_pauli_sum<T, NQ, W, CNOT>(RY, RV, CNOT ? RX : RY, S, S + N1, sp, cp, L, true, lane, wave);
 
     // reverse sweep: x in lanes 0..31, lambda in lanes 32..63
     double* g = grad + row * P;
