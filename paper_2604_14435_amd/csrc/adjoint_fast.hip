@@ -208,7 +208,10 @@ __device__ __forceinline__ void grad_undo_range_ladder(T* re, T* im, int lane, c
 }
 
 // Sum of the 32 partials of each qubit of the layer into g[0..NQ), by the
-// first NQ threads of the block.
+// first NQ threads of the block, after a barrier (the partials of every
+// wavefront written).  No barrier after it: consecutive layers write
+// alternate partial buffers, and a buffer is written again only after the
+// next layer's flush barrier, which the reading threads reach once done.
 template <int NQ>
 __device__ __forceinline__ void flush_grad(const double* gb, double* __restrict__ g, int tid) {
     __syncthreads();
@@ -224,7 +227,6 @@ __device__ __forceinline__ void flush_grad(const double* gb, double* __restrict_
         }
         g[tid] = (s0 + s1) + (s2 + s3);
     }
-    __syncthreads();
 }
 
 // Layout swap into the ladder frame, the inverse of relayout_ladder: the
@@ -491,7 +493,7 @@ __host__ __device__ constexpr size_t wave_adjoint_lds(int layers, int L) {
     constexpr int regions = ENT == DVQ_ENT_CZ_LADDER ? 3 : 4;    // x, y/lambda, v (+ x in the ladder frame)
     return (size_t)(2 * N + (2 * N) / 32) * sizeof(cplx<T>)      // scratch for layout swaps
            + regions * (size_t)(N + N / 32) * sizeof(cplx<T>)
-           + (size_t)NQ * 33 * sizeof(double)                    // gradient partials
+           + (size_t)2 * NQ * 33 * sizeof(double)                // gradient partials, two buffers
            + (size_t)2 * NQ * layers * sizeof(T);                // rotation table
 }
 
@@ -511,8 +513,8 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
     cplx<T>* RV = RY + N1;
     constexpr bool CNOT = ENT == DVQ_ENT_CNOT_LADDER;
     cplx<T>* RXF = RV + N1;  // x in the ladder frame (CNOT ladder only)
-    double* gb = reinterpret_cast<double*>(CNOT ? RXF + N1 : RV + N1);  // gradient partials [NQ][33]
-    T* trig = reinterpret_cast<T*>(gb + NQ * 33);
+    double* gb = reinterpret_cast<double*>(CNOT ? RXF + N1 : RV + N1);  // gradient partials [2][NQ][33]
+    T* trig = reinterpret_cast<T*>(gb + 2 * NQ * 33);
     // W wavefronts per row: each runs the register phases redundantly (same
     // values written to the same LDS slots, every hand-over fenced by a
     // barrier) and takes 1/W of the Pauli sums; wavefront 0 writes the results.
@@ -659,6 +661,8 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
 
     // reverse sweep: x in lanes 0..31, lambda in lanes 32..63
     double* g = grad + row * P;
+    // layer l's partials go to buffer l mod 2 (see flush_grad)
+    auto gbl = [&](int l) { return gb + (l & 1) * NQ * 33; };
     if constexpr (CNOT) {
         constexpr int RB = Lay<NQ, false>::RB;
         if (pf)
@@ -670,24 +674,24 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
             if (l & 1) {
                 // odd layer (forward: HI qubits in the frame, swap to LO,
                 // LO qubits 0..4): starts in LO, true state of its RYs
-                grad_undo_range<T, NQ, false, 0, W, 0, 5>(re, im, lane, trig, kb, gb, wave);
+                grad_undo_range<T, NQ, false, 0, W, 0, 5>(re, im, lane, trig, kb, gbl(l), wave);
                 relayout_to_ladder<T, NQ, false>(re, im, S, lane);
-                grad_undo_range_ladder<T, NQ, true, W, 5, NQ>(re, im, lane, trig, kb, gb, wave);
+                grad_undo_range_ladder<T, NQ, true, W, 5, NQ>(re, im, lane, trig, kb, gbl(l), wave);
             } else {
                 // even layer >= 2 (forward: LO qubits 0..RB-1 in the frame,
                 // swap to HI, HI qubits 5..NQ-1): starts in HI
-                grad_undo_range<T, NQ, true, 0, W, 5, NQ>(re, im, lane, trig, kb, gb, wave);
+                grad_undo_range<T, NQ, true, 0, W, 5, NQ>(re, im, lane, trig, kb, gbl(l), wave);
                 relayout_to_ladder<T, NQ, true>(re, im, S, lane);
                 // qubit RB-1 across lane bit 0 when it is below 5 (else in HI above)
-                grad_undo_range_ladder<T, NQ, false, W, 0, RB - 1, (RB - 1 < 5)>(re, im, lane, trig, kb, gb, wave);
+                grad_undo_range_ladder<T, NQ, false, W, 0, RB - 1, (RB - 1 < 5)>(re, im, lane, trig, kb, gbl(l), wave);
             }
-            flush_grad<NQ>(gb, g + kb, threadIdx.x);
+            flush_grad<NQ>(gbl(l), g + kb, threadIdx.x);
         }
         // layer 0 (forward: LO qubits, plain swap, HI qubits RB..NQ-1): starts in HI
-        grad_undo_range<T, NQ, true, 0, W, RB, NQ>(re, im, lane, trig, 0, gb, wave);
+        grad_undo_range<T, NQ, true, 0, W, RB, NQ>(re, im, lane, trig, 0, gbl(0), wave);
         relayout<T, NQ, true>(re, im, S, lane);
-        grad_undo_range<T, NQ, false, 0, W, 0, NQ>(re, im, lane, trig, 0, gb, wave);
-        flush_grad<NQ>(gb, g, threadIdx.x);
+        grad_undo_range<T, NQ, false, 0, W, 0, NQ>(re, im, lane, trig, 0, gbl(0), wave);
+        flush_grad<NQ>(gbl(0), g, threadIdx.x);
         if (threadIdx.x == 0) Cout[row] = cost;
         return;
     }
@@ -695,25 +699,25 @@ k_adjoint_wave(const double* __restrict__ theta, int layers, const dvq_c128* __r
     if (pf) {
         // last layer even-indexed: ended in HI with p = 1 after its ladder
         load_halves<T, NQ, true>(re, im, RX, RY, lane, 1);
-        grad_undo_range<T, NQ, true, 0, W, Lay<NQ, false>::RB, NQ>(re, im, lane, trig, l * NQ, gb, wave);
+        grad_undo_range<T, NQ, true, 0, W, Lay<NQ, false>::RB, NQ>(re, im, lane, trig, l * NQ, gbl(l), wave);
         relayout<T, NQ, true>(re, im, S, lane);
-        grad_undo_range<T, NQ, false, 0, W, 0, NQ>(re, im, lane, trig, l * NQ, gb, wave);
-        flush_grad<NQ>(gb, g + l * NQ, threadIdx.x);
+        grad_undo_range<T, NQ, false, 0, W, 0, NQ>(re, im, lane, trig, l * NQ, gbl(l), wave);
+        flush_grad<NQ>(gbl(l), g + l * NQ, threadIdx.x);
         --l;
     } else {
         load_halves<T, NQ, false>(re, im, RX, RY, lane, 0);
     }
     for (; l >= 1; l -= 2) {
         // odd layer l (p = 1 during its RYs): LO qubits 0..4, swap, HI qubits
-        grad_undo_range<T, NQ, false, 1, W, 0, 5>(re, im, lane, trig, l * NQ, gb, wave);
+        grad_undo_range<T, NQ, false, 1, W, 0, 5>(re, im, lane, trig, l * NQ, gbl(l), wave);
         relayout<T, NQ, false>(re, im, S, lane);
-        grad_undo_range<T, NQ, true, 1, W, 0, NQ>(re, im, lane, trig, l * NQ, gb, wave);
-        flush_grad<NQ>(gb, g + l * NQ, threadIdx.x);
+        grad_undo_range<T, NQ, true, 1, W, 0, NQ>(re, im, lane, trig, l * NQ, gbl(l), wave);
+        flush_grad<NQ>(gbl(l), g + l * NQ, threadIdx.x);
         // even layer l - 1 (p = 0): HI qubits RB..NQ-1, swap, LO qubits
-        grad_undo_range<T, NQ, true, 0, W, Lay<NQ, false>::RB, NQ>(re, im, lane, trig, (l - 1) * NQ, gb, wave);
+        grad_undo_range<T, NQ, true, 0, W, Lay<NQ, false>::RB, NQ>(re, im, lane, trig, (l - 1) * NQ, gbl(l - 1), wave);
         relayout<T, NQ, true>(re, im, S, lane);
-        grad_undo_range<T, NQ, false, 0, W, 0, NQ>(re, im, lane, trig, (l - 1) * NQ, gb, wave);
-        flush_grad<NQ>(gb, g + (l - 1) * NQ, threadIdx.x);
+        grad_undo_range<T, NQ, false, 0, W, 0, NQ>(re, im, lane, trig, (l - 1) * NQ, gbl(l - 1), wave);
+        flush_grad<NQ>(gbl(l - 1), g + (l - 1) * NQ, threadIdx.x);
     }
     if (threadIdx.x == 0) Cout[row] = cost;
 }
