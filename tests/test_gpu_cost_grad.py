@@ -248,13 +248,15 @@ def test_register_adjoint_cnot_bench_system(layers):
             assert np.max(np.abs(g[0].cpu().numpy() - g0)) < tol_g, (kind, precision)
 
 
-@pytest.mark.parametrize("ent,precision", [("cz", "f64"), ("cnot", "f32"), ("cnot", "f64")])
-def test_register_adjoint_strings_beyond_one_block(ent, precision):
-    """L = 100 at n = 10: the Pauli sums take strings 64 at a time and eight
-    per batch, so this runs one full block, a second block of 36 and a
-    remainder of 4; vs the exact shift rule, local and global cost."""
+@pytest.mark.parametrize("ent,precision,L", [("cz", "f64", 100), ("cnot", "f32", 100), ("cnot", "f64", 100),
+                                            ("cz", "f32", 3), ("cnot", "f64", 1)])
+def test_register_adjoint_string_counts(ent, precision, L):
+    """The four wavefronts split the strings of each Pauli sum (a quarter
+    each, read 64 per load, two per batch): L = 100 gives 25 per wavefront
+    (a batch remainder), L = 3 and L = 1 leave wavefronts without strings;
+    vs the exact shift rule, local and global cost."""
     n, layers = 10, 2
-    A, At, c, xs, zs, strings = _system(n, 1.0, -0.4, top_L=100)
+    A, At, c, xs, zs, strings = _system(n, 1.0, -0.4, top_L=L)
     th = theta_uniform(n * layers, seed=5)
     an = api.AnsatzSpec(n, layers, ent)
     tol_c, tol_g = (1e-12, 1e-10) if precision == "f64" else (1e-6, 1e-5)
