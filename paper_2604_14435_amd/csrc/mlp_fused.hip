@@ -103,31 +103,37 @@ __host__ __device__ inline W16 w16_layout(void* base, int H) {
     return w;
 }
 
+// H a compile-time constant: the index splits are shifts (the layouts hold
+// at most 2^18 elements, 32-bit indices).
+template <int H>
 __global__ void __launch_bounds__(256)
-k_mlp_weights_bf16(const float* __restrict__ params, int H, int d_in, int d_out, W16 w) {
+k_mlp_weights_bf16(const float* __restrict__ params, int d_in, int d_out, W16 w) {
     const dvq_mlp_shape sh{d_in, H, d_out};
     const MlpOffsets o = offsets(sh);
-    const int64_t n1 = (int64_t)H * kFKin, n2 = (int64_t)H * H, n3 = (int64_t)kFDmax * H;
-    const int64_t total = n1 + 2 * n2 + 2 * n3;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    constexpr int n1 = H * kFKin, n2 = H * H, n3 = kFDmax * H;
+    constexpr int total = n1 + 2 * n2 + 2 * n3;
+    const float* W1 = params + o.W1;
+    const float* W2 = params + o.W2;
+    const float* W3 = params + o.W3;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
         if (e < n1) {
-            const int h = (int)(e / kFKin), i = (int)(e % kFKin);
-            w.w1[e] = to_bf16(i < d_in ? params[o.W1 + (int64_t)h * d_in + i] : 0.f);
+            const int h = e / kFKin, i = e % kFKin;
+            w.w1[e] = to_bf16(i < d_in ? W1[h * d_in + i] : 0.f);
         } else if (e < n1 + n2) {
-            const int64_t x = e - n1;
-            w.w2[x] = to_bf16(params[o.W2 + x]);
+            const int x = e - n1;
+            w.w2[x] = to_bf16(W2[x]);
         } else if (e < n1 + 2 * n2) {
-            const int64_t x = e - n1 - n2;
-            const int r = (int)(x / H), c = (int)(x % H);
-            w.w2t[x] = to_bf16(params[o.W2 + (int64_t)c * H + r]);
+            const int x = e - n1 - n2;
+            const int r = x / H, c = x % H;
+            w.w2t[x] = to_bf16(W2[c * H + r]);
         } else if (e < n1 + 2 * n2 + n3) {
-            const int64_t x = e - n1 - 2 * n2;
-            const int d = (int)(x / H), k = (int)(x % H);
-            w.w3[x] = to_bf16(d < d_out ? params[o.W3 + (int64_t)d * H + k] : 0.f);
+            const int x = e - n1 - 2 * n2;
+            const int d = x / H, k = x % H;
+            w.w3[x] = to_bf16(d < d_out ? W3[d * H + k] : 0.f);
         } else {
-            const int64_t x = e - n1 - 2 * n2 - n3;
-            const int h = (int)(x / kFDmax), d = (int)(x % kFDmax);
-            w.w3t[x] = to_bf16(d < d_out ? params[o.W3 + (int64_t)d * H + h] : 0.f);
+            const int x = e - n1 - 2 * n2 - n3;
+            const int h = x / kFDmax, d = x % kFDmax;
+            w.w3t[x] = to_bf16(d < d_out ? W3[d * H + h] : 0.f);
         }
     }
 }
@@ -633,8 +639,13 @@ dvq_status dvq_mlp_train_step(const dvq_mlp_shape* shape, float* params, float* 
     const W16 w = w16_layout(static_cast<char*>(workspace) + part, s.hidden);
     hipStream_t hs = stream_of(stream);
     const int64_t welems = (int64_t)w16_elems(s.hidden);
-    hipLaunchKernelGGL(k_mlp_weights_bf16, dim3((unsigned)((welems + 255) / 256 < 1024 ? (welems + 255) / 256 : 1024)),
-                       dim3(256), 0, hs, params, s.hidden, s.d_in, s.d_out, w);
+    const dim3 wgrid((unsigned)((welems + 255) / 256 < 1024 ? (welems + 255) / 256 : 1024));
+    if (s.hidden == 64)
+        hipLaunchKernelGGL(k_mlp_weights_bf16<64>, wgrid, dim3(256), 0, hs, params, s.d_in, s.d_out, w);
+    else if (s.hidden == 128)
+        hipLaunchKernelGGL(k_mlp_weights_bf16<128>, wgrid, dim3(256), 0, hs, params, s.d_in, s.d_out, w);
+    else
+        hipLaunchKernelGGL(k_mlp_weights_bf16<256>, wgrid, dim3(256), 0, hs, params, s.d_in, s.d_out, w);
     DVQ_CHECK_LAUNCH("k_mlp_weights_bf16");
     if (s.hidden == 64)
         st = launch_train_chunks<64>(s, params, X, T, x_rows, rows, batch, feat_mean, feat_inv_std, w, pg, lossp, hs);
